@@ -1,0 +1,121 @@
+"""Statistics of a K sweep.
+
+Section 3 ("Timing, residency, statistics") and Section 4.2 fix the
+reporting rules this module implements:
+
+* the unit is the kernel launch; a cell's figure is the median over its
+  launches, and the best launch is kept as a separate raw field
+  (Section 4.1 reports median and best-of-N side by side);
+* the post-peak change is (B(K=8) - B(K=2)) / B(K=2) on per-K medians
+  (Section 4.2, Table 1), and per-launch paired changes are reported too
+  (Section 4.2, "Repeatability");
+* peak K and the knee follow a 95 % plateau rule with a stable three-cell
+  tail (Section 3; Section 4.2, "Prevalence").  The paper does not spell
+  the rule out; the reading used here: B* is the largest median, peak K
+  the smallest K attaining it, knee the smallest K with B >= 0.95 B*;
+  a curve is "saturating" if its last three cells are all >= 0.95 B*,
+  else "rising-censored" if the peak is among the last three cells, else
+  "peak-decline";
+* a residency screen flags HBM-targeted cells whose attained bandwidth
+  exceeds the HBM datasheet figure (Section 3).
+
+Little's law (Section 1, Section 2): offered bytes in flight equal
+bandwidth times latency, so in-flight bytes / bandwidth is the implied
+round-trip latency.
+"""
+import statistics
+
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E datasheet bandwidth
+INFINITY_CACHE_BYTES = 256 << 20  # MI355X last-level (MALL) cache
+
+
+def median(values):
+    """Median of a non-empty sequence."""
+    return statistics.median(list(values))
+
+
+def decline(b2, b8):
+    """(B8 - B2) / B2 as a fraction (negative for a decline)."""
+    if b2 <= 0:
+        raise ValueError("B(K=2) must be positive")
+    return (b8 - b2) / b2
+
+
+def per_k_medians(samples):
+    """{K: [GB/s per launch]} -> {K: median}."""
+    return {k: median(v) for k, v in samples.items() if len(v)}
+
+
+def paired_declines(samples, k_lo=2, k_hi=8):
+    """Per-launch changes B8[i]/B2[i] - 1 for launches present at both K."""
+    a, b = samples[k_lo], samples[k_hi]
+    return [decline(x, y) for x, y in zip(a, b)]
+
+
+def peak_k(medians):
+    """Smallest K whose median equals the largest median."""
+    best = max(medians.values())
+    return min(k for k, v in medians.items() if v == best)
+
+
+def knee(medians, frac=0.95):
+    """Smallest K whose median reaches frac * max median."""
+    best = max(medians.values())
+    return min(k for k, v in medians.items() if v >= frac * best)
+
+
+def classify(medians, frac=0.95, tail=3):
+    """Regime of a response curve: saturating / rising-censored / peak-decline."""
+    ks = sorted(medians)
+    if len(ks) < tail:
+        raise ValueError("curve shorter than the stable tail")
+    best = max(medians.values())
+    last = ks[-tail:]
+    if all(medians[k] >= frac * best for k in last):
+        return "saturating"
+    if peak_k(medians) in last:
+        return "rising-censored"
+    return "peak-decline"
+
+
+def residency_flag(gbps, cell_bytes, datasheet_gbps=HBM_PEAK_GBPS,
+                   cache_bytes=INFINITY_CACHE_BYTES):
+    """True if an HBM-targeted cell reports more than the datasheet allows.
+
+    Cells whose buffer fits in the last-level cache are not HBM-targeted and
+    are never flagged (they may legitimately exceed the HBM figure).
+    """
+    return cell_bytes > cache_bytes and gbps > datasheet_gbps
+
+
+def kset_mismatch(issued):
+    """(max - min) / max over a K set's issued logical loads."""
+    hi, lo = max(issued), min(issued)
+    return (hi - lo) / hi
+
+
+def in_flight_bytes(n_waves, K, vec_bytes, lanes=64):
+    """Offered bytes in flight: every lane of every resident wave has K loads."""
+    return n_waves * lanes * K * vec_bytes
+
+
+def implied_latency_ns(in_flight, gbps):
+    """Little's law: latency = bytes in flight / bandwidth (GB/s = bytes/ns)."""
+    return in_flight / gbps
+
+
+def summarize_curve(samples):
+    """Summary of one response curve {K: [GB/s per launch]}."""
+    med = per_k_medians(samples)
+    out = {
+        "median_gbps": {int(k): v for k, v in sorted(med.items())},
+        "best_gbps": {int(k): max(v) for k, v in sorted(samples.items())},
+        "min_gbps": {int(k): min(v) for k, v in sorted(samples.items())},
+        "peak_K": peak_k(med),
+        "knee_K": knee(med),
+        "regime": classify(med) if len(med) >= 3 else None,
+    }
+    if 2 in med and 8 in med:
+        out["decline_2_8"] = decline(med[2], med[8])
+        out["paired_declines_2_8"] = paired_declines(samples)
+    return out

@@ -1,0 +1,137 @@
+"""Pins for the oracle's address map and checksum sinks."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import brute, checksums, plan, splitmix
+
+
+def _buf(nbytes, seed=11):
+    return splitmix.buffer_words(seed, nbytes)
+
+
+CASES = [
+    # V, K, Q, n_waves, buffer bytes (n_vec * V); includes wrap-around
+    (4, 1, 5, 2, 4 * 64 * 4),
+    (4, 3, 7, 3, 4 * 64 * 5),       # ragged: Q not a multiple of n_waves
+    (8, 2, 6, 4, 8 * 64 * 3),       # issued 768 vectors over 192: 4 passes
+    (16, 5, 3, 2, 16 * 64 * 7),     # 960 of 448 vectors: wraps mid-group
+    (16, 16, 2, 1, 16 * 64 * 4),
+    (16, 1, 9, 4, 16 * 64 * 64),    # less than one pass
+    (8, 7, 4, 3, 8 * 64 * 2),       # group larger than the buffer
+]
+
+
+@pytest.mark.parametrize("V,K,Q,nw,nbytes", CASES)
+def test_vectorised_lanes_match_brute_force(V, K, Q, nw, nbytes):
+    w = _buf(nbytes)
+    lanes = brute.simulate(w, V, K, Q, nw)
+    s, x = checksums.per_lane(w, V, K, Q, nw)
+    for (wave, lane), (ls, lx) in lanes.items():
+        assert s[wave, lane] == ls and x[wave, lane] == lx
+
+
+@pytest.mark.parametrize("V,K,Q,nw,nbytes", CASES)
+def test_vectorised_waves_match_brute_force(V, K, Q, nw, nbytes):
+    w = _buf(nbytes, seed=12)
+    bs, bx = brute.per_wave(brute.simulate(w, V, K, Q, nw), nw)
+    s, x = checksums.per_wave(w, V, K, Q, nw, chunk_groups=2)
+    assert s.tolist() == bs and x.tolist() == bx
+
+
+@pytest.mark.parametrize("V,K,Q,nw,nbytes", CASES)
+def test_seeded_single_wave_and_lane(V, K, Q, nw, nbytes):
+    seed = 12345
+    w = _buf(nbytes, seed=seed)
+    s, x = checksums.per_wave(w, V, K, Q, nw)
+    ls, lx = checksums.per_lane(w, V, K, Q, nw)
+    for wave in range(nw):
+        assert checksums.wave_from_seed(seed, V, K, Q, nw, wave,
+                                        buffer_bytes=nbytes) == (s[wave], x[wave])
+        for lane in (0, 17, 63):
+            assert checksums.lane_from_seed(seed, V, K, Q, nw, wave, lane,
+                                            nbytes // V) == (ls[wave, lane], lx[wave, lane])
+
+
+def test_region_offset_matches_brute_force():
+    V, K, Q, nw = 16, 3, 5, 2
+    w = _buf(16 * 64 * 8)
+    base, n_vec = 192, 128
+    lanes = brute.simulate(w, V, K, Q, nw, base=base, n_vec=n_vec)
+    s, x = checksums.per_lane(w, V, K, Q, nw, base=base, n_vec=n_vec)
+    for (wave, lane), (ls, lx) in lanes.items():
+        assert (s[wave, lane], x[wave, lane]) == (ls, lx)
+
+
+def test_closed_form_passes_plus_prefix():
+    # global sinks over m full passes plus a prefix of r vectors:
+    # sum = m * S + S_prefix (mod 2**32); xor = (X if m odd) ^ X_prefix
+    V, K, nw = 16, 4, 3
+    n_vec = 64 * 9
+    w = _buf(n_vec * V, seed=3)
+    S, X = checksums.whole_buffer(w)
+    for Q in (1, 2, 8, 9, 20, 21, 33):
+        issued = 64 * K * Q
+        m, r = divmod(issued, n_vec)
+        ps, px = checksums.whole_buffer(w[:r * V // 4])
+        want_s = (m * S + ps) & 0xFFFFFFFF
+        want_x = (X if m % 2 else 0) ^ px
+        s, x = checksums.per_wave(w, V, K, Q, nw)
+        assert checksums.combine(s, x) == (want_s, want_x)
+
+
+def test_xor_cancels_on_even_passes_but_sum_does_not():
+    V, K, nw = 4, 2, 2
+    n_vec = 64 * 4
+    w = _buf(n_vec * V, seed=4)
+    S, X = checksums.whole_buffer(w)
+    Q = 2 * n_vec // (64 * K)
+    s, x = checksums.combine(*checksums.per_wave(w, V, K, Q, nw))
+    assert x == 0 and s == (2 * S) & 0xFFFFFFFF and s != 0
+
+
+def test_one_full_pass_is_independent_of_K_and_grid():
+    # the invariant the GPU sweep relies on: every power-of-two K at fixed
+    # work issues one full pass, so the global sinks equal the whole buffer
+    V = 16
+    n_vec = 64 * 64
+    w = _buf(n_vec * V, seed=5)
+    want = checksums.whole_buffer(w)
+    for K, nw in itertools.product((1, 2, 4, 8, 16), (1, 3, 16)):
+        p = plan.wave_group(n_vec, K, nw)
+        assert p["issued"] == n_vec
+        got = checksums.combine(*checksums.per_wave(w, V, K, p["Q"], nw))
+        assert got == want
+
+
+def test_lanes_fold_into_waves():
+    V, K, Q, nw = 8, 3, 11, 4
+    w = _buf(8 * 64 * 10, seed=6)
+    ls, lx = checksums.per_lane(w, V, K, Q, nw)
+    s, x = checksums.per_wave(w, V, K, Q, nw)
+    assert ((ls.astype(np.uint64).sum(axis=1) & 0xFFFFFFFF) == s).all()
+    assert (np.bitwise_xor.reduce(lx, axis=1) == x).all()
+
+
+def test_every_instruction_is_one_coalesced_segment():
+    # lane l of a load reads vector base + l: 64 consecutive vectors
+    K, n_vec = 5, 64 * 7
+    for q in range(6):
+        for j in range(K):
+            v = [checksums.vector_index(q, j, l, K, n_vec) for l in range(64)]
+            assert v == list(range(v[0], v[0] + 64))
+
+
+def test_two_stream_regions_partition_the_buffer():
+    V, nw = 16, 2
+    n_vec = 64 * 10
+    w = _buf(n_vec * V, seed=8)
+    (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
+    assert a0 == 0 and a0 + an == b0 and b0 + bn == n_vec
+    K = 1
+    sa, xa = checksums.per_wave(w, V, K, an // 64, nw, base=a0, n_vec=an)
+    sb, xb = checksums.per_wave(w, V, K, bn // 64, nw, base=b0, n_vec=bn)
+    s = (checksums.combine(sa, xa)[0] + checksums.combine(sb, xb)[0]) & 0xFFFFFFFF
+    x = checksums.combine(sa, xa)[1] ^ checksums.combine(sb, xb)[1]
+    assert (s, x) == checksums.whole_buffer(w)

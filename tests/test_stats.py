@@ -1,0 +1,96 @@
+"""Pins for the sweep statistics against the paper's printed numbers."""
+import json
+import os
+
+import pytest
+
+from conftest import GOLDEN
+from paper_2608_15764_amd import stats
+
+
+def _t1():
+    with open(os.path.join(GOLDEN, "table1_decline.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("row", _t1()["rows"], ids=lambda r: r["arm"])
+def test_table1_changes(row):
+    # the medians are printed to 0.1 GB/s and the change to 0.1 %, so the
+    # change computed from any medians that round to the printed ones must
+    # round-overlap the printed change
+    b2, b8, h = row["K2"], row["K8"], 0.05
+    lo = 100 * stats.decline(b2 + h, b8 - h)
+    hi = 100 * stats.decline(b2 - h, b8 + h)
+    p = float(row["change_percent"])
+    assert lo - 1e-9 <= p + 0.05 and p - 0.05 <= hi + 1e-9
+    # and the point value is within one printed step
+    assert abs(100 * stats.decline(b2, b8) - p) <= 0.1
+    # the other plausible denominator (B8) is far off
+    assert abs(100 * (b8 - b2) / b8 - p) > 10
+
+
+def test_decline_sign_and_zero():
+    assert stats.decline(100.0, 100.0) == 0.0
+    assert stats.decline(100.0, 50.0) == -0.5
+    with pytest.raises(ValueError):
+        stats.decline(0.0, 1.0)
+
+
+def test_medians_resist_two_anomalous_launches():
+    # ten launches shaped like the Repeatability paragraph: eight agree to
+    # 0.6 %, launch 9 runs up to 8 % slow, launch 10 at about half speed
+    spread = [-0.002, -0.001, -0.0005, 0.0, 0.0, 0.0005, 0.001, 0.002]
+    base = {1: 2200.0, 2: 3050.0, 4: 2500.0, 8: 1980.0}
+    samples = {k: [b * (1 + d) for d in spread] for k, b in base.items()}
+    # launch 9: slow, paired change -32.9 %; launch 10: half speed, -43.0 %
+    for k in base:
+        samples[k].append(base[k] * 0.92)
+        samples[k].append(base[k] * 0.5)
+    samples[8][8] = samples[2][8] * (1 - 0.329)
+    samples[8][9] = samples[2][9] * (1 - 0.430)
+    full = stats.decline(stats.median(samples[2]), stats.median(samples[8]))
+    kept = {k: v[:8] for k, v in samples.items()}
+    trimmed = stats.decline(stats.median(kept[2]), stats.median(kept[8]))
+    lim = _t1()["repeatability"]["max_median_shift_pp"]
+    assert abs(100 * (full - trimmed)) < lim
+    # whereas a mean would move by far more
+    mean = lambda v: sum(v) / len(v)
+    md = stats.decline(mean(samples[2]), mean(samples[8]))
+    assert abs(100 * (md - trimmed)) > lim
+
+
+def test_peak_knee_and_regimes():
+    rising = {k: float(k) for k in range(1, 9)}
+    assert stats.classify(rising) == "rising-censored"
+    assert stats.peak_k(rising) == 8
+    flat = {1: 50.0, 2: 99.0, 3: 100.0, 4: 100.0, 5: 99.5, 6: 98.0}
+    assert stats.classify(flat) == "saturating"
+    assert stats.knee(flat) == 2
+    peak = {1: 80.0, 2: 100.0, 3: 90.0, 4: 80.0, 5: 70.0, 6: 65.0}
+    assert stats.classify(peak) == "peak-decline"
+    assert stats.peak_k(peak) == 2
+    tie = {1: 1.0, 2: 5.0, 3: 5.0, 4: 1.0}
+    assert stats.peak_k(tie) == 2
+
+
+def test_residency_screen():
+    big = 1 << 30
+    assert stats.residency_flag(8500.0, big)
+    assert not stats.residency_flag(7000.0, big)
+    assert not stats.residency_flag(20000.0, 64 << 20)   # cache-resident cell
+
+
+def test_littles_law():
+    # the paper's H100 figures: 3,350 GB/s x 353 ns ~ 1.18 MB in flight
+    assert abs(3350 * 353 - 1.18e6) / 1.18e6 < 0.01
+    fl = stats.in_flight_bytes(n_waves=1024, K=2, vec_bytes=16)
+    assert fl == 1024 * 64 * 2 * 16
+    assert stats.implied_latency_ns(fl, 2097.152) == pytest.approx(1000.0)
+
+
+def test_summary_curve():
+    s = {1: [1.0, 1.1], 2: [3.0, 3.2], 4: [2.5, 2.4], 8: [2.0, 2.1]}
+    out = stats.summarize_curve(s)
+    assert out["peak_K"] == 2
+    assert out["decline_2_8"] == pytest.approx((2.05 - 3.1) / 3.1)
+    assert len(out["paired_declines_2_8"]) == 2
