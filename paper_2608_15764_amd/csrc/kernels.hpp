@@ -1,0 +1,98 @@
+// Kernel argument blocks and host-side launch entry points of the gfx950
+// kernels.  Each kernel family lives in its own translation unit and is
+// reached from the runtime only through the functions declared here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ilpsweep.h"
+
+namespace ilp {
+
+constexpr int kMaxK = 16;
+constexpr int kPlainWgThreads = 256;   // 4 waves, one per SIMD
+
+// Plain K-load cell.  Wave w of n_waves handles wave-groups q = w, w +
+// n_waves, ... below Q; load j of group q reads the 64 vectors starting at
+// vector (q*K + j)*64 mod n_vec.  `stride` is (n_waves*K*64) mod n_vec.
+struct PlainArgs {
+  const uint8_t* buf;
+  uint64_t n_vec;
+  uint64_t Q;
+  uint64_t stride;
+  sweep_wave_rec_t* rec;
+  uint32_t* lane_out;
+};
+
+// LDS-ring cell (async or matched), `waves` waves per workgroup.
+struct LdsArgs {
+  const uint8_t* buf;
+  uint64_t n_vec;
+  uint64_t Q;
+  uint64_t stride;        // (n_waves*D*64) mod n_vec
+  sweep_wave_rec_t* rec;
+  uint32_t* lane_out;
+  uint32_t waves;         // waves per workgroup
+};
+
+// Two co-resident streams: A (plain K = D) on region A, B (LDS-async ring
+// of depth D) on region B.  Records of A come first (n_waves_a of them),
+// then those of B.
+struct TwoStreamArgs {
+  const uint8_t* buf_a;
+  uint64_t n_vec_a, Q_a, stride_a;
+  const uint8_t* buf_b;
+  uint64_t n_vec_b, Q_b, stride_b;
+  sweep_wave_rec_t* rec;   // n_waves_a + n_waves_b records
+  uint32_t* lane_out;      // lanes of A then lanes of B, or null
+  uint32_t waves_a, waves_b;  // per workgroup
+};
+
+// Precision variant: full wave-groups of 4 loads x 64 lanes x 16 bytes,
+// then the ragged remainder (whole 16-byte vectors, then the last bytes).
+struct ReduceArgs {
+  const uint8_t* payload;
+  uint64_t n_groups;        // full 4 KiB wave-groups
+  uint64_t n_vec;           // whole 16-byte vectors
+  uint64_t n_bytes;         // payload bytes
+  float* partials;          // 2 floats (s, c) per workgroup
+  sweep_wave_rec_t* rec;
+};
+
+// Per-cell result reduced on the device from the wave records.
+struct CellRes {
+  uint64_t sum;   // low 32 bits used
+  uint64_t xr;    // low 32 bits used
+  uint64_t tmin;
+  uint64_t tmax;
+};
+
+// ---- plain (kernels_plain.hip)
+const void* plain_kernel(int K, int V, int policy);
+hipError_t launch_plain(int K, int V, int policy, uint32_t grid,
+                        size_t lds_bytes, hipStream_t st, const PlainArgs& a);
+
+// ---- LDS paths (kernels_lds.hip)
+const void* lds_kernel(int kind, int D, int policy);
+hipError_t launch_lds(int kind, int D, int policy, uint32_t grid,
+                      uint32_t wg_threads, size_t lds_bytes, hipStream_t st,
+                      const LdsArgs& a);
+const void* two_stream_kernel(int D, int policy);
+hipError_t launch_two_stream(int D, int policy, uint32_t grid,
+                             uint32_t wg_threads, size_t lds_bytes,
+                             hipStream_t st, const TwoStreamArgs& a);
+
+// ---- fill, finishing, clock, reduction (kernels_misc.hip)
+hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,
+                       hipStream_t st);
+hipError_t launch_finish(const sweep_wave_rec_t* rec, uint32_t n_waves,
+                         CellRes* out, hipStream_t st);
+hipError_t launch_read_clock(uint64_t* out, hipStream_t st);
+const void* reduce_kernel(int dtype);
+hipError_t launch_reduce(int dtype, uint32_t grid, hipStream_t st,
+                         const ReduceArgs& a);
+hipError_t launch_reduce_finish(const float* partials, uint32_t n,
+                                double* out, hipStream_t st);
+
+}  // namespace ilp

@@ -1,0 +1,88 @@
+// Plain K-load sweep kernel (the hot loop of the method, Section 3 "The
+// axis K" and Section 4.2).
+//
+// One wavefront-iteration issues K independent loads - each one contiguous,
+// coalesced 64-lane segment of 64*V bytes - into K distinct register sets,
+// and only then folds them, oldest first; nothing from the next iteration is
+// in flight meanwhile, so a wave has at most K loads outstanding.  The loop
+// itself never stores: the sinks leave the kernel in one record per wave.
+#include <array>
+#include <utility>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace ilp {
+
+template <int K, int V, int POL>
+__global__ __launch_bounds__(kPlainWgThreads) void plain_kload(PlainArgs a) {
+  const uint64_t t0 = wall_ticks();
+  const uint32_t lane = lane_id();
+  const uint32_t wid = blockIdx.x * (kPlainWgThreads / kWave) + wave_in_wg();
+  const uint32_t n_waves = gridDim.x * (kPlainWgThreads / kWave);
+
+  uint32_t s = 0, x = 0;
+  // start vector of this wave's first group, and the per-iteration step,
+  // both modulo the buffer's vector count (wave-uniform, scalar registers)
+  uint64_t p = ((uint64_t)wid * (K * kWave)) % a.n_vec;
+#pragma unroll 1
+  for (uint64_t q = wid; q < a.Q; q += n_waves) {
+    typename Vec<V>::T v[K];
+    uint64_t pj = p;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      v[j] = load_seg<V, POL>(a.buf + pj * V, lane);
+      pj += kWave;
+      if (pj >= a.n_vec) pj -= a.n_vec;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) fold(v[j], s, x);
+    p += a.stride;
+    if (p >= a.n_vec) p -= a.n_vec;
+  }
+  const uint64_t t1 = wall_ticks();
+  wave_epilogue(s, x, t0, t1, wid, a.rec, a.lane_out);
+}
+
+namespace {
+
+typedef void (*PlainFn)(PlainArgs);
+
+template <int V, int POL, int... Ks>
+constexpr std::array<PlainFn, sizeof...(Ks)> row(std::integer_sequence<int, Ks...>) {
+  return {&plain_kload<Ks + 1, V, POL>...};
+}
+
+template <int V, int POL>
+constexpr auto kRow = row<V, POL>(std::make_integer_sequence<int, kMaxK>{});
+
+// [vector width index][policy][K-1]
+const PlainFn* table(int vi, int pol) {
+  static const std::array<PlainFn, kMaxK> t[3][3] = {
+      {kRow<4, 0>, kRow<4, 1>, kRow<4, 2>},
+      {kRow<8, 0>, kRow<8, 1>, kRow<8, 2>},
+      {kRow<16, 0>, kRow<16, 1>, kRow<16, 2>},
+  };
+  return t[vi][pol].data();
+}
+
+int width_index(int V) { return V == 4 ? 0 : V == 8 ? 1 : V == 16 ? 2 : -1; }
+
+}  // namespace
+
+const void* plain_kernel(int K, int V, int policy) {
+  const int vi = width_index(V);
+  if (vi < 0 || K < 1 || K > kMaxK || policy < 0 || policy > 2) return nullptr;
+  return reinterpret_cast<const void*>(table(vi, policy)[K - 1]);
+}
+
+hipError_t launch_plain(int K, int V, int policy, uint32_t grid,
+                        size_t lds_bytes, hipStream_t st, const PlainArgs& a) {
+  const void* fn = plain_kernel(K, V, policy);
+  if (!fn) return hipErrorInvalidValue;
+  void* args[] = {const_cast<PlainArgs*>(&a)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kPlainWgThreads), args,
+                         lds_bytes, st);
+}
+
+}  // namespace ilp

@@ -1,0 +1,770 @@
+// Host runtime behind the C ABI of include/ilpsweep.h: per-device state and
+// scratch, validation through the planner, occupancy checks, launches on
+// the caller's stream with hipEvents, per-cell finishing, the back-to-back
+// sweep driver, the hipGraph-batched sweep, the autotuner and the clock
+// calibration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "ilpsweep.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace ilp;
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, std::string msg) {
+  t_err = std::move(msg);
+  return code;
+}
+
+#define HIP_TRY(x)                                                          \
+  do {                                                                      \
+    hipError_t e__ = (x);                                                   \
+    if (e__ != hipSuccess)                                                  \
+      return fail(SWEEP_EHIP, std::string(#x) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+#define SW_TRY(x)           \
+  do {                      \
+    int r__ = (x);          \
+    if (r__ != SWEEP_OK) return r__; \
+  } while (0)
+
+struct Dev {
+  int ordinal = -1;
+  char arch[64] = {0};
+  uint32_t num_cus = 0, lds_per_cu = 0, lds_per_wg_max = 0, l2 = 0;
+  uint64_t hbm = 0;
+  double nominal_hz = 0, cal_hz = 0;
+  int clock_khz = 0, mem_khz = 0, bus_bits = 0;
+  sweep_wave_rec_t* rec = nullptr;
+  size_t rec_cap = 0;
+  CellRes* res = nullptr;
+  size_t res_cap = 0;
+  CellRes* res_h = nullptr;   // pinned host copy
+  size_t res_h_cap = 0;
+  float* partials = nullptr;
+  size_t partials_cap = 0;
+  double* dsum = nullptr;
+  double* dsum_h = nullptr;
+  uint64_t* clk = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipStream_t capture = nullptr;
+  double hz() const { return cal_hz > 0 ? cal_hz : nominal_hz; }
+};
+
+std::mutex g_mu;
+std::map<int, Dev*> g_devs;
+
+template <class T>
+int ensure_dev(T*& p, size_t& cap, size_t n) {
+  if (n <= cap) return SWEEP_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  if (hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SWEEP_ENOMEM, "device scratch allocation failed");
+  }
+  cap = n;
+  return SWEEP_OK;
+}
+
+template <class T>
+int ensure_host(T*& p, size_t& cap, size_t n) {
+  if (n <= cap) return SWEEP_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(n, 1) * sizeof(T),
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SWEEP_ENOMEM, "pinned host allocation failed");
+  }
+  cap = n;
+  return SWEEP_OK;
+}
+
+int ensure_events(Dev& d, size_t n) {
+  while (d.ev.size() < n) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    d.ev.push_back(e);
+  }
+  return SWEEP_OK;
+}
+
+int init_device(int ordinal, Dev** out) {
+  auto it = g_devs.find(ordinal);
+  if (it != g_devs.end()) {
+    *out = it->second;
+    return SWEEP_OK;
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ordinal));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SWEEP_ENODEV, std::string("library is built for gfx950, device is ") +
+                                  prop.gcnArchName);
+  Dev* d = new Dev();
+  d->ordinal = ordinal;
+  std::strncpy(d->arch, prop.gcnArchName, sizeof(d->arch) - 1);
+  d->num_cus = (uint32_t)prop.multiProcessorCount;
+  d->lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
+  d->lds_per_wg_max = (uint32_t)prop.sharedMemPerBlock;
+  d->l2 = (uint32_t)prop.l2CacheSize;
+  d->hbm = (uint64_t)prop.totalGlobalMem;
+  d->clock_khz = prop.clockRate;
+  d->mem_khz = prop.memoryClockRate;
+  d->bus_bits = prop.memoryBusWidth;
+  int wc_khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, ordinal));
+  d->nominal_hz = wc_khz > 0 ? wc_khz * 1000.0 : 1.0e8;
+  // scratch for the largest default grid (32 waves per CU)
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)d->num_cus * 32));
+  SW_TRY(ensure_dev(d->res, d->res_cap, 64));
+  SW_TRY(ensure_host(d->res_h, d->res_h_cap, 64));
+  size_t one = 0, one_h = 0, clk_cap = 0;
+  SW_TRY(ensure_dev(d->dsum, one, 1));
+  SW_TRY(ensure_host(d->dsum_h, one_h, 1));
+  SW_TRY(ensure_dev(d->clk, clk_cap, 1));
+  SW_TRY(ensure_events(*d, 8));
+  g_devs[ordinal] = d;
+  *out = d;
+  return SWEEP_OK;
+}
+
+int current_dev(Dev** out) {
+  int ord = 0;
+  HIP_TRY(hipGetDevice(&ord));
+  return init_device(ord, out);
+}
+
+// ----------------------------------------------------------- cell prep
+struct Prepared {
+  sweep_cell_t c{};
+  Plan plan{};
+  const void* fn = nullptr;
+  uint32_t grid = 0, threads = 0;
+  size_t lds = 0;
+  int max_wgs = 0;
+  hipFuncAttributes fa{};
+};
+
+int prepare(const Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
+  PlanIn in;
+  in.bytes = c.bytes;
+  in.K = c.K;
+  in.V = c.vec_width;
+  in.kind = c.kind;
+  in.waves_per_cu = c.waves_per_cu;
+  in.L = c.total_logical_loads;
+  in.mode = c.mode;
+  in.fixed_iters = c.fixed_iters;
+  in.num_cus = d.num_cus;
+  in.grid_wgs = c.grid_wgs;
+  in.lds_per_cu = d.lds_per_cu;
+  in.lds_per_wg_max = d.lds_per_wg_max;
+  Prepared p;
+  p.c = c;
+  std::string err;
+  int rc = plan_cell(in, &p.plan, &err);
+  if (rc != SWEEP_OK) return fail(rc, err);
+  if (c.buf == nullptr) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(c.buf) % 16)
+    return fail(SWEEP_EALIGN, "buffer must be 16-byte aligned");
+  if (c.cache_policy < 0 || c.cache_policy > 2)
+    return fail(SWEEP_EINVAL, "unknown cache policy");
+  p.fn = c.kind == SWEEP_KIND_PLAIN ? plain_kernel(c.K, c.vec_width, c.cache_policy)
+                                    : lds_kernel(c.kind, c.K, c.cache_policy);
+  if (!p.fn) return fail(SWEEP_EINVAL, "no kernel for this cell");
+  p.grid = p.plan.pub.grid_wgs;
+  p.threads = p.plan.pub.wg_threads;
+  p.lds = p.plan.lds_ring_bytes;
+  if (pin && p.plan.pub.lds_pad_bytes > p.lds) p.lds = p.plan.pub.lds_pad_bytes;
+  HIP_TRY(hipFuncGetAttributes(&p.fa, p.fn));
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p.fn, (int)p.threads, p.lds));
+  p.max_wgs = nb;
+  if ((uint32_t)nb < p.plan.wgs_per_cu)
+    return fail(SWEEP_EOCCUPANCY,
+                "kernel resources allow " + std::to_string(nb) +
+                    " workgroups per CU, the cell needs " +
+                    std::to_string(p.plan.wgs_per_cu) + " (VGPRs " +
+                    std::to_string(p.fa.numRegs) + ", LDS " + std::to_string(p.lds) + ")");
+  *out = p;
+  return SWEEP_OK;
+}
+
+hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
+                   uint32_t* lane_out, CellRes* slot, hipEvent_t e0, hipEvent_t e1) {
+  hipError_t e = hipSuccess;
+  if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
+  if (p.c.kind == SWEEP_KIND_PLAIN) {
+    PlainArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+                p.plan.stride, rec, lane_out};
+    e = launch_plain(p.c.K, p.c.vec_width, p.c.cache_policy, p.grid, p.lds, st, a);
+  } else {
+    LdsArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+              p.plan.stride, rec, lane_out, p.plan.wg_waves};
+    e = launch_lds(p.c.kind, p.c.K, p.c.cache_policy, p.grid, p.threads, p.lds, st, a);
+  }
+  if (e != hipSuccess) return e;
+  if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
+  return launch_finish(rec, p.plan.pub.waves, slot, st);
+}
+
+void fill_result(const Dev& d, const Prepared& p, const CellRes& r, double ms,
+                 sweep_result_t* o) {
+  sweep_result_t x;
+  std::memset(&x, 0, sizeof(x));
+  x.target_loads = p.c.total_logical_loads;
+  x.issued_loads = p.plan.pub.issued_loads;
+  x.issued_bytes = p.plan.pub.issued_bytes;
+  x.mismatch = p.plan.pub.mismatch;
+  x.sum32 = (uint32_t)r.sum;
+  x.xor32 = (uint32_t)r.xr;
+  x.grid_wgs = p.grid;
+  x.wg_threads = p.threads;
+  x.waves = p.plan.pub.waves;
+  x.iters_min = p.plan.pub.iters_min;
+  x.iters_max = p.plan.pub.iters_max;
+  x.max_wgs_per_cu = (uint32_t)p.max_wgs;
+  x.vgprs = (uint32_t)p.fa.numRegs;
+  x.sgprs = 0;
+  x.lds_bytes = (uint32_t)(p.lds + p.fa.sharedSizeBytes);
+  x.scratch_bytes = (uint32_t)p.fa.localSizeBytes;
+  x.window_ticks = r.tmax >= r.tmin ? r.tmax - r.tmin : 0;
+  x.window_ns = (double)x.window_ticks / d.hz() * 1e9;
+  x.event_ms = ms;
+  x.gbps = x.window_ns > 0 ? (double)x.issued_bytes / x.window_ns : 0.0;
+  *o = x;
+}
+
+hipStream_t as_stream(const sweep_opts_t* o) {
+  return o ? static_cast<hipStream_t>(o->stream) : nullptr;
+}
+
+sweep_cell_t cell_from(int kind, const void* buf, size_t bytes, int K, int V,
+                       int waves, uint64_t L, const sweep_opts_t* o) {
+  sweep_cell_t c;
+  std::memset(&c, 0, sizeof(c));
+  c.kind = kind;
+  c.K = K;
+  c.vec_width = V;
+  c.waves_per_cu = waves;
+  c.cache_policy = o ? o->cache_policy : SWEEP_CACHE_DEFAULT;
+  c.mode = o ? o->mode : SWEEP_FIXED_WORK;
+  c.fixed_iters = o ? o->fixed_iters : 0;
+  c.grid_wgs = o ? o->grid_wgs : 0;
+  c.buf = buf;
+  c.bytes = bytes;
+  c.total_logical_loads = L;
+  return c;
+}
+
+int pin_of(const sweep_opts_t* o) { return o ? o->pin_occupancy : 1; }
+
+// Runs prepared cells back to back; one synchronisation at the end.
+int run_prepared(Dev& d, std::vector<Prepared>& ps, hipStream_t st,
+                 sweep_wave_rec_t* wave_out, uint32_t* lane_out,
+                 sweep_result_t* results) {
+  const size_t n = ps.size();
+  size_t max_waves = 0;
+  for (auto& p : ps) max_waves = std::max<size_t>(max_waves, p.plan.pub.waves);
+  SW_TRY(ensure_dev(d.rec, d.rec_cap, max_waves));
+  SW_TRY(ensure_dev(d.res, d.res_cap, n));
+  SW_TRY(ensure_host(d.res_h, d.res_h_cap, n));
+  SW_TRY(ensure_events(d, 2 * n + 1));
+  for (size_t i = 0; i < n; ++i) {
+    sweep_wave_rec_t* rec = wave_out ? wave_out : d.rec;
+    HIP_TRY(enqueue(ps[i], st, rec, lane_out, d.res + i, d.ev[2 * i], d.ev[2 * i + 1]));
+  }
+  HIP_TRY(hipMemcpyAsync(d.res_h, d.res, n * sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(d.ev[2 * n], st));
+  HIP_TRY(hipEventSynchronize(d.ev[2 * n]));
+  for (size_t i = 0; i < n; ++i) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, d.ev[2 * i], d.ev[2 * i + 1]));
+    fill_result(d, ps[i], d.res_h[i], ms, &results[i]);
+  }
+  return SWEEP_OK;
+}
+
+int single_cell(const sweep_cell_t& c, const sweep_opts_t* opt, sweep_result_t* out) {
+  if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  std::vector<Prepared> ps(1);
+  SW_TRY(prepare(*d, c, pin_of(opt), &ps[0]));
+  sweep_result_t r;
+  SW_TRY(run_prepared(*d, ps, as_stream(opt), opt ? opt->wave_out : nullptr,
+                      opt ? opt->lane_out : nullptr, &r));
+  *out = r;
+  return SWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sweep_init(int ordinal) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (ordinal < 0 || ordinal >= n) return fail(SWEEP_ENODEV, "no such device");
+  HIP_TRY(hipSetDevice(ordinal));
+  Dev* d = nullptr;
+  return init_device(ordinal, &d);
+}
+
+int sweep_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_devs) {
+    Dev* d = kv.second;
+    (void)hipSetDevice(d->ordinal);
+    (void)hipDeviceSynchronize();
+    if (d->rec) (void)hipFree(d->rec);
+    if (d->res) (void)hipFree(d->res);
+    if (d->res_h) (void)hipHostFree(d->res_h);
+    if (d->partials) (void)hipFree(d->partials);
+    if (d->dsum) (void)hipFree(d->dsum);
+    if (d->dsum_h) (void)hipHostFree(d->dsum_h);
+    if (d->clk) (void)hipFree(d->clk);
+    for (auto e : d->ev) (void)hipEventDestroy(e);
+    if (d->capture) (void)hipStreamDestroy(d->capture);
+    delete d;
+  }
+  g_devs.clear();
+  (void)hipSetDevice(cur);
+  return SWEEP_OK;
+}
+
+int sweep_device_info(sweep_device_t* out) {
+  if (!out) return fail(SWEEP_EINVAL, "NULL output");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  sweep_device_t o;
+  std::memset(&o, 0, sizeof(o));
+  o.ordinal = d->ordinal;
+  std::strncpy(o.arch, d->arch, sizeof(o.arch) - 1);
+  o.num_cus = d->num_cus;
+  o.lds_per_cu = d->lds_per_cu;
+  o.lds_per_wg_max = d->lds_per_wg_max;
+  o.l2_bytes = d->l2;
+  o.hbm_bytes = d->hbm;
+  o.wall_clock_hz = d->nominal_hz;
+  o.calibrated_hz = d->cal_hz;
+  o.clock_khz = d->clock_khz;
+  o.mem_clock_khz = d->mem_khz;
+  o.mem_bus_bits = d->bus_bits;
+  *out = o;
+  return SWEEP_OK;
+}
+
+int sweep_calibrate_clock(double seconds, double* hz) {
+  if (!hz || !(seconds >= 0.01) || seconds > 60) return fail(SWEEP_EINVAL, "seconds must be in [0.01, 60]");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  using clk = std::chrono::steady_clock;
+  auto sample = [&](uint64_t* ticks, double* ns) -> int {
+    double best_span = 1e300;
+    for (int rep = 0; rep < 5; ++rep) {
+      const auto a = clk::now();
+      HIP_TRY(launch_read_clock(d->clk, nullptr));
+      HIP_TRY(hipStreamSynchronize(nullptr));
+      const auto b = clk::now();
+      uint64_t t = 0;
+      HIP_TRY(hipMemcpy(&t, d->clk, sizeof(t), hipMemcpyDeviceToHost));
+      const double span = std::chrono::duration<double, std::nano>(b - a).count();
+      if (span < best_span) {
+        best_span = span;
+        *ticks = t;
+        *ns = std::chrono::duration<double, std::nano>(a.time_since_epoch()).count() + span / 2;
+      }
+    }
+    return SWEEP_OK;
+  };
+  uint64_t t1 = 0, t2 = 0;
+  double n1 = 0, n2 = 0;
+  SW_TRY(sample(&t1, &n1));
+  std::this_thread::sleep_for(std::chrono::duration<double>(seconds));
+  SW_TRY(sample(&t2, &n2));
+  if (t2 <= t1 || n2 <= n1) return fail(SWEEP_EHIP, "device clock did not advance");
+  d->cal_hz = (double)(t2 - t1) / ((n2 - n1) * 1e-9);
+  *hz = d->cal_hz;
+  return SWEEP_OK;
+}
+
+int sweep_plan(size_t bytes, int K, int vec_width, int waves_per_cu,
+               uint64_t total_logical_loads, int mode, uint32_t fixed_iters,
+               uint32_t num_cus, uint32_t grid_wgs, sweep_plan_t* out) {
+  if (!out) return fail(SWEEP_EINVAL, "NULL output");
+  PlanIn in;
+  in.bytes = bytes;
+  in.K = K;
+  in.V = vec_width;
+  in.kind = SWEEP_KIND_PLAIN;
+  in.waves_per_cu = waves_per_cu;
+  in.L = total_logical_loads;
+  in.mode = mode;
+  in.fixed_iters = fixed_iters;
+  in.num_cus = num_cus;
+  in.grid_wgs = grid_wgs;
+  Plan p;
+  std::string err;
+  int rc = plan_cell(in, &p, &err);
+  if (rc != SWEEP_OK) return fail(rc, err);
+  *out = p.pub;
+  return SWEEP_OK;
+}
+
+int sweep_fill_u32(void* buf, size_t bytes, uint64_t seed, void* stream) {
+  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
+  if (bytes == 0) return fail(SWEEP_EINVAL, "empty buffer");
+  if (bytes % 4 || reinterpret_cast<uintptr_t>(buf) % 16)
+    return fail(SWEEP_EALIGN, "fill needs a 16-byte aligned buffer of whole words");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  HIP_TRY(launch_fill(static_cast<uint32_t*>(buf), bytes / 4, seed,
+                      static_cast<hipStream_t>(stream)));
+  return SWEEP_OK;
+}
+
+int sweep_plain(const void* buf, size_t bytes, int K, int vec_width,
+                int waves_per_cu, uint64_t total_logical_loads,
+                const sweep_opts_t* opt, sweep_result_t* out) {
+  return single_cell(cell_from(SWEEP_KIND_PLAIN, buf, bytes, K, vec_width,
+                               waves_per_cu, total_logical_loads, opt),
+                     opt, out);
+}
+
+int sweep_lds_async(const void* buf, size_t bytes, int depth, int vec_width,
+                    int waves_per_cu, uint64_t total_logical_loads,
+                    const sweep_opts_t* opt, sweep_result_t* out) {
+  return single_cell(cell_from(SWEEP_KIND_LDS_ASYNC, buf, bytes, depth,
+                               vec_width, waves_per_cu, total_logical_loads, opt),
+                     opt, out);
+}
+
+int sweep_lds_matched_plain(const void* buf, size_t bytes, int depth,
+                            int vec_width, int waves_per_cu,
+                            uint64_t total_logical_loads,
+                            const sweep_opts_t* opt, sweep_result_t* out) {
+  return single_cell(cell_from(SWEEP_KIND_LDS_MATCHED, buf, bytes, depth,
+                               vec_width, waves_per_cu, total_logical_loads, opt),
+                     opt, out);
+}
+
+int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
+                     int waves_async, uint64_t total_logical_loads,
+                     const sweep_opts_t* opt, sweep_result_t out[2]) {
+  if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
+  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
+  if (depth < 1 || depth > 16) return fail(SWEEP_EINVAL, "depth must be in 1..16");
+  if (waves_plain < 0 || waves_plain > 8 || waves_async < 0 || waves_async > 8 ||
+      waves_plain + waves_async == 0)
+    return fail(SWEEP_EINVAL, "waves_plain and waves_async must be in 0..8, not both 0");
+  if (bytes == 0) return fail(SWEEP_EINVAL, "empty buffer");
+  if (bytes % 2048 || reinterpret_cast<uintptr_t>(buf) % 16)
+    return fail(SWEEP_EALIGN, "two-stream needs a 16-byte aligned buffer, bytes % 2048 == 0");
+  if (total_logical_loads == 0) return fail(SWEEP_EINVAL, "total_logical_loads is 0");
+  const int pol = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
+  if (pol < 0 || pol > 2) return fail(SWEEP_EINVAL, "unknown cache policy");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  const uint32_t grid = (opt && opt->grid_wgs) ? opt->grid_wgs : d->num_cus;
+  const uint64_t n_vec = bytes / 16, half = n_vec / 2;
+  const uint64_t La = total_logical_loads / 2, Lb = total_logical_loads - La;
+  TwoStreamArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.buf_a = static_cast<const uint8_t*>(buf);
+  a.n_vec_a = half;
+  a.buf_b = static_cast<const uint8_t*>(buf) + half * 16;
+  a.n_vec_b = n_vec - half;
+  a.waves_a = (uint32_t)waves_plain;
+  a.waves_b = (uint32_t)waves_async;
+  if (waves_plain) region_plan(a.n_vec_a, depth, La, grid * a.waves_a, &a.Q_a, &a.stride_a);
+  if (waves_async) region_plan(a.n_vec_b, depth, Lb, grid * a.waves_b, &a.Q_b, &a.stride_b);
+  if ((waves_plain && a.Q_a == 0) || (waves_async && a.Q_b == 0))
+    return fail(SWEEP_EINVAL, "L is smaller than one wave-group per stream");
+  const uint32_t threads = (uint32_t)(waves_plain + waves_async) * 64u;
+  const uint32_t ring = (uint32_t)waves_async * (uint32_t)depth * 1024u;
+  if (ring > d->lds_per_wg_max) return fail(SWEEP_EOCCUPANCY, "LDS ring exceeds the per-workgroup LDS");
+  size_t lds = ring;
+  if (pin_of(opt)) lds = std::max<size_t>(lds, pin_padding(1, ring, d->lds_per_cu, d->lds_per_wg_max));
+  const void* fn = two_stream_kernel(depth, pol);
+  hipFuncAttributes fa;
+  HIP_TRY(hipFuncGetAttributes(&fa, fn));
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds));
+  if (nb < 1) return fail(SWEEP_EOCCUPANCY, "two-stream workgroup does not fit a CU");
+  const uint32_t wa = grid * a.waves_a, wb = grid * a.waves_b;
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)wa + wb));
+  SW_TRY(ensure_events(*d, 3));
+  sweep_wave_rec_t* rec = (opt && opt->wave_out) ? opt->wave_out : d->rec;
+  a.rec = rec;
+  a.lane_out = opt ? opt->lane_out : nullptr;
+  hipStream_t st = as_stream(opt);
+  HIP_TRY(hipEventRecord(d->ev[0], st));
+  HIP_TRY(launch_two_stream(depth, pol, grid, threads, lds, st, a));
+  HIP_TRY(hipEventRecord(d->ev[1], st));
+  HIP_TRY(launch_finish(rec, wa, d->res, st));
+  HIP_TRY(launch_finish(rec + wa, wb, d->res + 1, st));
+  HIP_TRY(hipMemcpyAsync(d->res_h, d->res, 2 * sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(d->ev[2], st));
+  HIP_TRY(hipEventSynchronize(d->ev[2]));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+  for (int s = 0; s < 2; ++s) {
+    const bool on = s == 0 ? waves_plain > 0 : waves_async > 0;
+    Prepared p;
+    p.c = cell_from(s == 0 ? SWEEP_KIND_PLAIN : SWEEP_KIND_LDS_ASYNC, buf, bytes,
+                    depth, 16, s == 0 ? waves_plain : waves_async,
+                    s == 0 ? La : Lb, opt);
+    p.grid = grid;
+    p.threads = threads;
+    p.lds = lds;
+    p.max_wgs = nb;
+    p.fa = fa;
+    const uint64_t Q = s == 0 ? a.Q_a : a.Q_b;
+    const uint32_t nw = s == 0 ? wa : wb;
+    p.plan.pub.grid_wgs = grid;
+    p.plan.pub.wg_threads = threads;
+    p.plan.pub.waves = nw;
+    p.plan.pub.n_vec = s == 0 ? a.n_vec_a : a.n_vec_b;
+    p.plan.pub.Q = Q;
+    p.plan.pub.issued_loads = 64ull * (uint64_t)depth * Q;
+    p.plan.pub.issued_bytes = p.plan.pub.issued_loads * 16ull;
+    p.plan.pub.iters_min = nw ? (uint32_t)(Q / nw) : 0;
+    p.plan.pub.iters_max = nw ? (uint32_t)((Q + nw - 1) / nw) : 0;
+    const uint64_t Ls = s == 0 ? La : Lb;
+    p.plan.pub.mismatch = Ls ? (double)(Ls - p.plan.pub.issued_loads) / (double)Ls : 0.0;
+    if (on) {
+      fill_result(*d, p, d->res_h[s], ms, &out[s]);
+    } else {
+      std::memset(&out[s], 0, sizeof(out[s]));
+    }
+  }
+  return SWEEP_OK;
+}
+
+int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
+              sweep_result_t* results) {
+  if (!cells || !results || n <= 0) return fail(SWEEP_EINVAL, "empty cell list");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  std::vector<Prepared> ps((size_t)n);
+  for (int i = 0; i < n; ++i) SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
+  return run_prepared(*d, ps, as_stream(opt), nullptr, nullptr, results);
+}
+
+int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
+                  sweep_result_t* results, double* graph_ms) {
+  if (!cells || !results || n <= 0) return fail(SWEEP_EINVAL, "empty cell list");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  std::vector<Prepared> ps((size_t)n);
+  size_t max_waves = 0;
+  for (int i = 0; i < n; ++i) {
+    SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
+    max_waves = std::max<size_t>(max_waves, ps[(size_t)i].plan.pub.waves);
+  }
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, max_waves));
+  SW_TRY(ensure_dev(d->res, d->res_cap, (size_t)n));
+  SW_TRY(ensure_host(d->res_h, d->res_h_cap, (size_t)n));
+  SW_TRY(ensure_events(*d, 3));
+  if (!d->capture) HIP_TRY(hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
+  hipError_t cap_err = hipSuccess;
+  for (int i = 0; i < n && cap_err == hipSuccess; ++i)
+    cap_err = enqueue(ps[(size_t)i], d->capture, d->rec, nullptr, d->res + i, nullptr, nullptr);
+  hipError_t end_err = hipStreamEndCapture(d->capture, &graph);
+  if (cap_err != hipSuccess || end_err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(SWEEP_EHIP, std::string("graph capture failed: ") +
+                                hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(SWEEP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  }
+  hipStream_t st = as_stream(opt);
+  hipError_t le = hipEventRecord(d->ev[0], st);
+  if (le == hipSuccess) le = hipGraphLaunch(exec, st);
+  if (le == hipSuccess) le = hipEventRecord(d->ev[1], st);
+  if (le == hipSuccess)
+    le = hipMemcpyAsync(d->res_h, d->res, (size_t)n * sizeof(CellRes), hipMemcpyDeviceToHost, st);
+  if (le == hipSuccess) le = hipEventRecord(d->ev[2], st);
+  if (le == hipSuccess) le = hipEventSynchronize(d->ev[2]);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  if (le != hipSuccess) return fail(SWEEP_EHIP, std::string("graph launch: ") + hipGetErrorString(le));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+  if (graph_ms) *graph_ms = ms;
+  for (int i = 0; i < n; ++i) fill_result(*d, ps[(size_t)i], d->res_h[i], 0.0, &results[i]);
+  return SWEEP_OK;
+}
+
+int sweep_autotune(const void* buf, size_t bytes, const int* vec_widths,
+                   int n_vec_widths, const int* Ks, int n_Ks,
+                   const int* waves_per_cu, int n_waves, int cache_policy,
+                   int reps, sweep_cell_t* best, double* best_gbps) {
+  if (!vec_widths || !Ks || !waves_per_cu || n_vec_widths <= 0 || n_Ks <= 0 ||
+      n_waves <= 0 || reps < 1 || !best || !best_gbps)
+    return fail(SWEEP_EINVAL, "empty candidate set or reps < 1");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  double top = -1.0;
+  sweep_cell_t top_cell;
+  std::memset(&top_cell, 0, sizeof(top_cell));
+  int last_err = SWEEP_OK;
+  for (int vi = 0; vi < n_vec_widths; ++vi)
+    for (int ki = 0; ki < n_Ks; ++ki)
+      for (int wi = 0; wi < n_waves; ++wi) {
+        sweep_cell_t c;
+        std::memset(&c, 0, sizeof(c));
+        c.kind = SWEEP_KIND_PLAIN;
+        c.K = Ks[ki];
+        c.vec_width = vec_widths[vi];
+        c.waves_per_cu = waves_per_cu[wi];
+        c.cache_policy = cache_policy;
+        c.mode = SWEEP_FIXED_WORK;
+        c.buf = buf;
+        c.bytes = bytes;
+        c.total_logical_loads = vec_widths[vi] > 0 ? bytes / (size_t)vec_widths[vi] : 0;
+        Prepared p;
+        int rc = prepare(*d, c, 1, &p);
+        if (rc == SWEEP_EOCCUPANCY || (rc == SWEEP_EINVAL && c.total_logical_loads > 0 &&
+                                       c.total_logical_loads < 64ull * (uint64_t)c.K)) {
+          last_err = rc;
+          continue;
+        }
+        if (rc != SWEEP_OK) return rc;
+        std::vector<Prepared> ps((size_t)reps + 1, p);
+        std::vector<sweep_result_t> rs((size_t)reps + 1);
+        SW_TRY(run_prepared(*d, ps, nullptr, nullptr, nullptr, rs.data()));
+        std::vector<double> g;
+        for (int r = 1; r <= reps; ++r) g.push_back(rs[(size_t)r].gbps);
+        std::sort(g.begin(), g.end());
+        const double med = g.size() % 2 ? g[g.size() / 2]
+                                        : 0.5 * (g[g.size() / 2 - 1] + g[g.size() / 2]);
+        if (med > top) {
+          top = med;
+          top_cell = c;
+        }
+      }
+  if (top < 0) return fail(last_err ? last_err : SWEEP_EINVAL, "no candidate could run");
+  *best = top_cell;
+  *best_gbps = top;
+  return SWEEP_OK;
+}
+
+int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
+                    int waves_per_cu, const sweep_opts_t* opt, double* sum,
+                    sweep_result_t* out) {
+  if (!sum) return fail(SWEEP_EINVAL, "sum pointer is NULL");
+  if (dtype != SWEEP_F32 && dtype != SWEEP_BF16 && dtype != SWEEP_FP8_E4M3)
+    return fail(SWEEP_EINVAL, "unknown dtype");
+  if (waves_per_cu < 4 || waves_per_cu > 32 || waves_per_cu % 4)
+    return fail(SWEEP_EINVAL, "waves_per_cu must be a multiple of 4 in 4..32");
+  if (n_elems && !payload) return fail(SWEEP_EINVAL, "payload pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(payload) % 16)
+    return fail(SWEEP_EALIGN, "payload must be 16-byte aligned");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  const size_t esz = dtype == SWEEP_F32 ? 4 : dtype == SWEEP_BF16 ? 2 : 1;
+  const uint32_t grid = (opt && opt->grid_wgs) ? opt->grid_wgs
+                                               : d->num_cus * (uint32_t)waves_per_cu / 4u;
+  ReduceArgs a;
+  a.payload = static_cast<const uint8_t*>(payload);
+  a.n_bytes = (uint64_t)n_elems * esz;
+  a.n_vec = a.n_bytes / 16;
+  a.n_groups = a.n_vec / 256;
+  if (a.n_vec - a.n_groups * 256 > (uint64_t)grid * 256)
+    return fail(SWEEP_EINVAL, "grid too small for the ragged remainder");
+  const void* fn = reduce_kernel(dtype);
+  hipFuncAttributes fa;
+  HIP_TRY(hipFuncGetAttributes(&fa, fn));
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0));
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)grid * 4));
+  SW_TRY(ensure_dev(d->partials, d->partials_cap, (size_t)grid * 2));
+  SW_TRY(ensure_events(*d, 3));
+  a.partials = d->partials;
+  a.rec = d->rec;
+  hipStream_t st = as_stream(opt);
+  HIP_TRY(hipEventRecord(d->ev[0], st));
+  HIP_TRY(launch_reduce(dtype, grid, st, a));
+  HIP_TRY(hipEventRecord(d->ev[1], st));
+  HIP_TRY(launch_reduce_finish(d->partials, grid, d->dsum, st));
+  HIP_TRY(launch_finish(d->rec, grid * 4, d->res, st));
+  HIP_TRY(hipMemcpyAsync(d->dsum_h, d->dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(d->res_h, d->res, sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(d->ev[2], st));
+  HIP_TRY(hipEventSynchronize(d->ev[2]));
+  *sum = *d->dsum_h;
+  if (out) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+    Prepared p;
+    p.c.total_logical_loads = a.n_vec;
+    p.grid = grid;
+    p.threads = 256;
+    p.max_wgs = nb;
+    p.fa = fa;
+    p.plan.pub.waves = grid * 4;
+    p.plan.pub.issued_loads = a.n_vec;
+    p.plan.pub.issued_bytes = a.n_bytes;
+    CellRes r = d->res_h[0];
+    r.sum = 0;
+    r.xr = 0;
+    fill_result(*d, p, r, ms, out);
+  }
+  return SWEEP_OK;
+}
+
+const char* sweep_strerror(int code) {
+  switch (code) {
+    case SWEEP_OK: return "success";
+    case SWEEP_EINVAL: return "invalid argument";
+    case SWEEP_EALIGN: return "alignment or size granularity violated";
+    case SWEEP_EOCCUPANCY: return "requested occupancy not achievable";
+    case SWEEP_EHIP: return "HIP runtime error";
+    case SWEEP_ENOMEM: return "scratch allocation failed";
+    case SWEEP_ENODEV: return "no usable gfx950 device";
+    default: return "unknown error";
+  }
+}
+
+const char* sweep_last_error(void) { return t_err.c_str(); }
+
+const char* sweep_version(void) { return "ilpsweep 0.1.0 (gfx950)"; }
+
+}  // extern "C"

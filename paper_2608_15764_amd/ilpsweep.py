@@ -1,0 +1,340 @@
+"""ctypes binding of the C ABI in ``include/ilpsweep.h``.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libilpsweep.so``.  Device pointers may be given as integers or as objects
+with a ``data_ptr()`` method (torch tensors); streams as integers, None (the
+null stream) or objects with a ``cuda_stream`` attribute.  A negative return
+code raises :class:`SweepError` carrying the library's error text.
+
+Importing this module fails loudly when the library has not been built.
+"""
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "libilpsweep.so")
+
+# ---------------------------------------------------------------- constants
+OK, EINVAL, EALIGN, EOCCUPANCY, EHIP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6
+FIXED_WORK, FIXED_ITERS, PER_THREAD_FLOOR = 0, 1, 2
+CACHE_DEFAULT, CACHE_NT, CACHE_BYPASS_L1 = 0, 1, 2
+KIND_PLAIN, KIND_LDS_ASYNC, KIND_LDS_MATCHED = 0, 1, 2
+F32, BF16, FP8_E4M3 = 0, 1, 2
+
+
+class sweep_wave_rec_t(C.Structure):
+    _fields_ = [("sum32", C.c_uint32), ("xor32", C.c_uint32),
+                ("hw_id", C.c_uint32), ("xcc_id", C.c_uint32),
+                ("t0", C.c_uint64), ("t1", C.c_uint64)]
+
+
+class sweep_opts_t(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("cache_policy", C.c_int),
+                ("mode", C.c_int), ("fixed_iters", C.c_uint32),
+                ("grid_wgs", C.c_uint32), ("pin_occupancy", C.c_int),
+                ("wave_out", C.c_void_p), ("lane_out", C.c_void_p)]
+
+
+class sweep_result_t(C.Structure):
+    _fields_ = [("target_loads", C.c_uint64), ("issued_loads", C.c_uint64),
+                ("issued_bytes", C.c_uint64), ("mismatch", C.c_double),
+                ("sum32", C.c_uint32), ("xor32", C.c_uint32),
+                ("grid_wgs", C.c_uint32), ("wg_threads", C.c_uint32),
+                ("waves", C.c_uint32), ("iters_min", C.c_uint32),
+                ("iters_max", C.c_uint32), ("max_wgs_per_cu", C.c_uint32),
+                ("vgprs", C.c_uint32), ("sgprs", C.c_uint32),
+                ("lds_bytes", C.c_uint32), ("scratch_bytes", C.c_uint32),
+                ("window_ticks", C.c_uint64), ("window_ns", C.c_double),
+                ("event_ms", C.c_double), ("gbps", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class sweep_plan_t(C.Structure):
+    _fields_ = [("grid_wgs", C.c_uint32), ("wg_threads", C.c_uint32),
+                ("waves", C.c_uint32), ("n_vec", C.c_uint64),
+                ("Q", C.c_uint64), ("issued_loads", C.c_uint64),
+                ("issued_bytes", C.c_uint64), ("iters_min", C.c_uint32),
+                ("iters_max", C.c_uint32), ("mismatch", C.c_double),
+                ("lds_pad_bytes", C.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class sweep_device_t(C.Structure):
+    _fields_ = [("ordinal", C.c_int), ("arch", C.c_char * 64),
+                ("num_cus", C.c_uint32), ("lds_per_cu", C.c_uint32),
+                ("lds_per_wg_max", C.c_uint32), ("l2_bytes", C.c_uint32),
+                ("hbm_bytes", C.c_uint64), ("wall_clock_hz", C.c_double),
+                ("calibrated_hz", C.c_double), ("clock_khz", C.c_int),
+                ("mem_clock_khz", C.c_int), ("mem_bus_bits", C.c_int)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["arch"] = self.arch.decode()
+        return d
+
+
+class sweep_cell_t(C.Structure):
+    _fields_ = [("kind", C.c_int), ("K", C.c_int), ("vec_width", C.c_int),
+                ("waves_per_cu", C.c_int), ("cache_policy", C.c_int),
+                ("mode", C.c_int), ("fixed_iters", C.c_uint32),
+                ("grid_wgs", C.c_uint32), ("buf", C.c_void_p),
+                ("bytes", C.c_size_t), ("total_logical_loads", C.c_uint64)]
+
+
+# symbol -> (restype, argtypes); every function declared in the header
+_P = C.c_void_p
+_SIG = {
+    "sweep_init": (C.c_int, [C.c_int]),
+    "sweep_shutdown": (C.c_int, []),
+    "sweep_device_info": (C.c_int, [C.POINTER(sweep_device_t)]),
+    "sweep_calibrate_clock": (C.c_int, [C.c_double, C.POINTER(C.c_double)]),
+    "sweep_plan": (C.c_int, [C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_uint64,
+                             C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
+                             C.POINTER(sweep_plan_t)]),
+    "sweep_fill_u32": (C.c_int, [_P, C.c_size_t, C.c_uint64, _P]),
+    "sweep_plain": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                              C.c_uint64, C.POINTER(sweep_opts_t),
+                              C.POINTER(sweep_result_t)]),
+    "sweep_lds_async": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                  C.c_uint64, C.POINTER(sweep_opts_t),
+                                  C.POINTER(sweep_result_t)]),
+    "sweep_lds_matched_plain": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int,
+                                          C.c_int, C.c_uint64,
+                                          C.POINTER(sweep_opts_t),
+                                          C.POINTER(sweep_result_t)]),
+    "sweep_two_stream": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                   C.c_uint64, C.POINTER(sweep_opts_t),
+                                   C.POINTER(sweep_result_t)]),
+    "sweep_run": (C.c_int, [C.POINTER(sweep_cell_t), C.c_int,
+                            C.POINTER(sweep_opts_t), C.POINTER(sweep_result_t)]),
+    "sweep_batched": (C.c_int, [C.POINTER(sweep_cell_t), C.c_int,
+                                C.POINTER(sweep_opts_t),
+                                C.POINTER(sweep_result_t),
+                                C.POINTER(C.c_double)]),
+    "sweep_autotune": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_int), C.c_int,
+                                 C.POINTER(C.c_int), C.c_int,
+                                 C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int,
+                                 C.POINTER(sweep_cell_t),
+                                 C.POINTER(C.c_double)]),
+    "sweep_reduce_fp": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int,
+                                  C.POINTER(sweep_opts_t),
+                                  C.POINTER(C.c_double),
+                                  C.POINTER(sweep_result_t)]),
+    "sweep_strerror": (C.c_char_p, [C.c_int]),
+    "sweep_last_error": (C.c_char_p, []),
+    "sweep_version": (C.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2608_15764_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class SweepError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        text = lib.sweep_last_error().decode() or lib.sweep_strerror(code).decode()
+        super().__init__(f"{where}: {lib.sweep_strerror(code).decode()} ({code}): {text}")
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise SweepError(rc, where)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return s.cuda_stream
+    return int(s)
+
+
+def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
+              fixed_iters=0, grid_wgs=0, pin_occupancy=True, wave_out=None,
+              lane_out=None):
+    o = sweep_opts_t()
+    o.stream = _stream(stream)
+    o.cache_policy = cache_policy
+    o.mode = mode
+    o.fixed_iters = fixed_iters
+    o.grid_wgs = grid_wgs
+    o.pin_occupancy = 1 if pin_occupancy else 0
+    o.wave_out = _ptr(wave_out)
+    o.lane_out = _ptr(lane_out)
+    return o
+
+
+# ------------------------------------------------------------ entry points
+def sweep_init(ordinal=0):
+    _check(lib.sweep_init(ordinal), "sweep_init")
+
+
+def sweep_shutdown():
+    _check(lib.sweep_shutdown(), "sweep_shutdown")
+
+
+def sweep_device_info():
+    d = sweep_device_t()
+    _check(lib.sweep_device_info(C.byref(d)), "sweep_device_info")
+    return d.as_dict()
+
+
+def sweep_calibrate_clock(seconds=0.2):
+    hz = C.c_double()
+    _check(lib.sweep_calibrate_clock(seconds, C.byref(hz)), "sweep_calibrate_clock")
+    return hz.value
+
+
+def sweep_plan(bytes_, K, vec_width, waves_per_cu, total_logical_loads,
+               mode=FIXED_WORK, fixed_iters=0, num_cus=256, grid_wgs=0):
+    p = sweep_plan_t()
+    _check(lib.sweep_plan(bytes_, K, vec_width, waves_per_cu,
+                          total_logical_loads, mode, fixed_iters, num_cus,
+                          grid_wgs, C.byref(p)), "sweep_plan")
+    return p.as_dict()
+
+
+def sweep_fill_u32(buf, bytes_, seed, stream=None):
+    _check(lib.sweep_fill_u32(_ptr(buf), bytes_, seed & (2**64 - 1),
+                              _stream(stream)), "sweep_fill_u32")
+
+
+def _cell_call(fn, name, buf, bytes_, K, vec_width, waves_per_cu, L, opts):
+    r = sweep_result_t()
+    o = opts if opts is not None else make_opts()
+    _check(fn(_ptr(buf), bytes_, K, vec_width, waves_per_cu, L, C.byref(o),
+              C.byref(r)), name)
+    return r.as_dict()
+
+
+def sweep_plain(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
+                opts=None):
+    return _cell_call(lib.sweep_plain, "sweep_plain", buf, bytes_, K,
+                      vec_width, waves_per_cu, total_logical_loads, opts)
+
+
+def sweep_lds_async(buf, bytes_, depth, vec_width, waves_per_cu,
+                    total_logical_loads, opts=None):
+    return _cell_call(lib.sweep_lds_async, "sweep_lds_async", buf, bytes_,
+                      depth, vec_width, waves_per_cu, total_logical_loads, opts)
+
+
+def sweep_lds_matched_plain(buf, bytes_, depth, vec_width, waves_per_cu,
+                            total_logical_loads, opts=None):
+    return _cell_call(lib.sweep_lds_matched_plain, "sweep_lds_matched_plain",
+                      buf, bytes_, depth, vec_width, waves_per_cu,
+                      total_logical_loads, opts)
+
+
+def sweep_two_stream(buf, bytes_, depth, waves_plain, waves_async,
+                     total_logical_loads, opts=None):
+    r = (sweep_result_t * 2)()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_two_stream(_ptr(buf), bytes_, depth, waves_plain,
+                                waves_async, total_logical_loads, C.byref(o),
+                                r), "sweep_two_stream")
+    return r[0].as_dict(), r[1].as_dict()
+
+
+def make_cell(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
+              kind=KIND_PLAIN, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
+              fixed_iters=0, grid_wgs=0):
+    c = sweep_cell_t()
+    c.kind = kind
+    c.K = K
+    c.vec_width = vec_width
+    c.waves_per_cu = waves_per_cu
+    c.cache_policy = cache_policy
+    c.mode = mode
+    c.fixed_iters = fixed_iters
+    c.grid_wgs = grid_wgs
+    c.buf = _ptr(buf)
+    c.bytes = bytes_
+    c.total_logical_loads = total_logical_loads
+    return c
+
+
+def _cells(cells):
+    arr = (sweep_cell_t * len(cells))()
+    for i, c in enumerate(cells):
+        arr[i] = c if isinstance(c, sweep_cell_t) else make_cell(**c)
+    return arr
+
+
+def sweep_run(cells, opts=None):
+    arr = _cells(cells)
+    res = (sweep_result_t * len(cells))()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_run(arr, len(cells), C.byref(o), res), "sweep_run")
+    return [r.as_dict() for r in res]
+
+
+def sweep_batched(cells, opts=None):
+    arr = _cells(cells)
+    res = (sweep_result_t * len(cells))()
+    o = opts if opts is not None else make_opts()
+    ms = C.c_double()
+    _check(lib.sweep_batched(arr, len(cells), C.byref(o), res, C.byref(ms)),
+           "sweep_batched")
+    return [r.as_dict() for r in res], ms.value
+
+
+def sweep_autotune(buf, bytes_, vec_widths, Ks, waves_per_cu,
+                   cache_policy=CACHE_DEFAULT, reps=3):
+    vw = (C.c_int * len(vec_widths))(*vec_widths)
+    ks = (C.c_int * len(Ks))(*Ks)
+    ws = (C.c_int * len(waves_per_cu))(*waves_per_cu)
+    best = sweep_cell_t()
+    g = C.c_double()
+    _check(lib.sweep_autotune(_ptr(buf), bytes_, vw, len(vw), ks, len(ks), ws,
+                              len(ws), cache_policy, reps, C.byref(best),
+                              C.byref(g)), "sweep_autotune")
+    return {"K": best.K, "vec_width": best.vec_width,
+            "waves_per_cu": best.waves_per_cu,
+            "cache_policy": best.cache_policy}, g.value
+
+
+def sweep_reduce_fp(payload, n_elems, dtype, waves_per_cu=32, opts=None):
+    s = C.c_double()
+    r = sweep_result_t()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_reduce_fp(_ptr(payload), n_elems, dtype, waves_per_cu,
+                               C.byref(o), C.byref(s), C.byref(r)),
+           "sweep_reduce_fp")
+    return s.value, r.as_dict()
+
+
+def sweep_strerror(code):
+    return lib.sweep_strerror(code).decode()
+
+
+def sweep_last_error():
+    return lib.sweep_last_error().decode()
+
+
+def sweep_version():
+    return lib.sweep_version().decode()

@@ -1,0 +1,48 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds none of the method's arithmetic: it only draws seeded
+random data with torch's generators, on the CPU or on a GPU, and hands the
+same bytes to both the HIP path and the CPU oracle.
+
+Recipes
+-------
+``random_bytes``  uniform bytes (any 32-bit word pattern), for checksum
+                  parity independent of the library's own seeded fill.
+``normal_payload``  N(0, 1) samples drawn in FP32 and stored as FP32, BF16
+                  (round to nearest even) or FP8 e4m3fn (clamped to +-448,
+                  then round to nearest even), as raw little-endian bytes.
+"""
+import torch
+
+DTYPES = {"f32": torch.float32, "bf16": torch.bfloat16,
+          "fp8_e4m3": torch.float8_e4m3fn}
+ELEM_BYTES = {"f32": 4, "bf16": 2, "fp8_e4m3": 1}
+
+
+def _gen(seed, device):
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def random_bytes(nbytes, seed, device="cpu"):
+    """uint8 tensor of ``nbytes`` uniform random bytes."""
+    g = _gen(seed, device)
+    return torch.randint(0, 256, (int(nbytes),), dtype=torch.uint8,
+                         generator=g, device=device)
+
+
+def normal_payload(kind, n, seed, device="cpu", chunk=1 << 26):
+    """uint8 tensor holding ``n`` N(0,1) values stored as ``kind``."""
+    dt = DTYPES[kind]
+    eb = ELEM_BYTES[kind]
+    out = torch.empty(int(n) * eb, dtype=torch.uint8, device=device)
+    g = _gen(seed, device)
+    view = out.view(dt) if n else None
+    for s in range(0, int(n), chunk):
+        c = min(chunk, int(n) - s)
+        x = torch.randn(c, dtype=torch.float32, generator=g, device=device)
+        if kind == "fp8_e4m3":
+            x = x.clamp_(-448.0, 448.0)
+        view[s:s + c] = x.to(dt)
+    return out

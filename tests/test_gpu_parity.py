@@ -1,0 +1,319 @@
+"""Parity of the HIP path against the CPU oracle, at sizes the oracle
+finishes in seconds (several tiles, ragged tails, wrap-around)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from gpu_util import (decode_lanes, decode_recs, dev_bytes, host_words,
+                      lanes, recs)
+from oracle import checksums, fpsum, plan as oplan, splitmix
+from paper_2608_15764_amd import ilpsweep as isw
+import synth
+
+SEED = 0x1D5EED00
+
+
+def test_device_is_gfx950():
+    info = isw.sweep_device_info()
+    print("device:", info, flush=True)
+    assert info["arch"].startswith("gfx950")
+    assert info["num_cus"] > 0 and info["lds_per_cu"] > 0
+
+
+@pytest.mark.parametrize("nbytes", [4, 12, 16, 1 << 20, (1 << 20) + 12,
+                                    3 * (1 << 20) + 4])
+def test_fill_matches_oracle(nbytes):
+    buf = torch.zeros(((nbytes + 15) // 16) * 16, dtype=torch.uint8, device="cuda")
+    isw.sweep_fill_u32(buf, nbytes, SEED + 7)
+    torch.cuda.synchronize()
+    got = host_words(buf)[:nbytes // 4]
+    assert np.array_equal(got, splitmix.words(SEED + 7, 0, nbytes // 4))
+    # nothing beyond the requested bytes is touched
+    assert not buf[nbytes:].any()
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_plumbing_cell_per_thread(K):
+    """64 MiB seeded buffer, 256 workgroups x 256 threads, 4-byte loads."""
+    nbytes = 64 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED)
+    L = nbytes // 4
+    n_waves = 1024
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=256, lane_out=lo, wave_out=ro)
+    r = isw.sweep_plain(buf, nbytes, K, 4, 4, L, opts)
+    p = oplan.wave_group(L, K, n_waves)
+    assert r["issued_loads"] == p["issued"] == L
+    words = splitmix.buffer_words(SEED, nbytes)
+    ws, wx = checksums.per_lane(words, 4, K, p["Q"], n_waves)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    rr = decode_recs(ro)
+    os_, ox = checksums.per_wave(words, 4, K, p["Q"], n_waves)
+    assert np.array_equal(rr["sum32"], os_) and np.array_equal(rr["xor32"], ox)
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words)
+
+
+PLAIN_CASES = [
+    # V, K, waves_per_cu, grid_wgs, n_vec, L (vectors)  -- wrap and ragged
+    (4, 1, 4, 3, 64 * 40, 64 * 40 * 3 + 77),
+    (4, 5, 8, 2, 64 * 17, 64 * 17 * 5 + 1000),
+    (8, 3, 4, 5, 64 * 33, 64 * 33 * 2),
+    (8, 16, 32, 1, 64 * 9, 64 * 16 * 11),
+    (16, 2, 4, 3, 64 * 64, 64 * 64 * 3 + 129),
+    (16, 7, 12, 2, 64 * 50, 64 * 7 * 23),
+    (16, 16, 8, 3, 64 * 20, 64 * 16 * 13),
+    (16, 1, 32, 4, 64 * 1024, 64 * 1024),
+]
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES)
+def test_plain_matches_oracle(V, K, w, grid, n_vec, L, policy):
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=V * 1000 + K, device="cuda")
+    n_waves = grid * 4
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=policy, lane_out=lo,
+                         wave_out=ro)
+    r = isw.sweep_plain(buf, nbytes, K, V, w, L, opts)
+    p = oplan.wave_group(L, K, n_waves)
+    assert r["issued_loads"] == p["issued"]
+    assert (r["iters_min"], r["iters_max"]) == (p["iters_min"], p["iters_max"])
+    words = host_words(buf)
+    ws, wx = checksums.per_lane(words, V, K, p["Q"], n_waves)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    rr = decode_recs(ro)
+    assert np.array_equal(rr["sum32"], ws.astype(np.uint64).sum(1).astype(np.uint32))
+    assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
+    assert (rr["t1"] >= rr["t0"]).all()
+
+
+@pytest.mark.parametrize("mode", ["fixed_iters", "per_thread_floor"])
+def test_plain_other_modes(mode):
+    V, K, grid = 16, 3, 2
+    n_vec = 64 * 30
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=5, device="cuda")
+    n_waves = grid * 4
+    ro = recs(n_waves)
+    if mode == "fixed_iters":
+        opts = isw.make_opts(grid_wgs=grid, mode=isw.FIXED_ITERS,
+                             fixed_iters=7, wave_out=ro)
+        r = isw.sweep_plain(buf, nbytes, K, V, 8, 0, opts)
+        o = oplan.fixed_iters(7, K, n_waves)
+    else:
+        L = 100000
+        opts = isw.make_opts(grid_wgs=grid, mode=isw.PER_THREAD_FLOOR, wave_out=ro)
+        r = isw.sweep_plain(buf, nbytes, K, V, 8, L, opts)
+        o = oplan.per_thread_floor(L, n_waves * 64, K)
+    assert r["issued_loads"] == o["issued"]
+    Q = o["issued"] // (64 * K)
+    s, x = checksums.per_wave(host_words(buf), V, K, Q, n_waves)
+    rr = decode_recs(ro)
+    assert np.array_equal(rr["sum32"], s) and np.array_equal(rr["xor32"], x)
+
+
+LDS_CASES = [
+    # kind, D, waves per WG, grid, n_vec, L
+    (1, 1, 1, 3, 64 * 40, 64 * 40 * 2 + 5),
+    (1, 4, 4, 2, 64 * 50, 64 * 4 * 31),
+    (1, 16, 8, 3, 64 * 20, 64 * 16 * 9),
+    (1, 5, 16, 1, 64 * 64, 64 * 5 * 40),
+    (2, 1, 1, 3, 64 * 40, 64 * 40 * 2 + 5),
+    (2, 4, 4, 2, 64 * 50, 64 * 4 * 31),
+    (2, 16, 8, 3, 64 * 20, 64 * 16 * 9),
+    (2, 3, 16, 1, 64 * 64, 64 * 3 * 40),
+]
+
+
+@pytest.mark.parametrize("policy", [0, 2])
+@pytest.mark.parametrize("kind,D,W,grid,n_vec,L", LDS_CASES)
+def test_lds_paths_match_oracle(kind, D, W, grid, n_vec, L, policy):
+    nbytes = n_vec * 16
+    buf = synth.random_bytes(nbytes, seed=D * 100 + W, device="cuda")
+    n_waves = grid * W
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=policy, lane_out=lo,
+                         wave_out=ro)
+    fn = isw.sweep_lds_async if kind == 1 else isw.sweep_lds_matched_plain
+    r = fn(buf, nbytes, D, 16, W, L, opts)
+    p = oplan.wave_group(L, D, n_waves)
+    assert r["issued_loads"] == p["issued"]
+    words = host_words(buf)
+    ws, wx = checksums.per_lane(words, 16, D, p["Q"], n_waves)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
+
+
+@pytest.mark.parametrize("D,wa,wb", [(4, 4, 4), (8, 4, 4), (3, 1, 3),
+                                     (5, 2, 0), (2, 0, 2), (16, 8, 8)])
+def test_two_stream_matches_oracle(D, wa, wb):
+    grid = 3
+    n_vec = 64 * 128
+    nbytes = n_vec * 16
+    buf = synth.random_bytes(nbytes, seed=D + 10 * wa + 100 * wb, device="cuda")
+    L = 2 * 64 * D * 37 + 64
+    na, nb = grid * wa, grid * wb
+    ro = recs(na + nb)
+    lo = lanes((na + nb) * 64)
+    opts = isw.make_opts(grid_wgs=grid, wave_out=ro, lane_out=lo)
+    ra, rb = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+    words = host_words(buf)
+    (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
+    rr = decode_recs(ro)
+    gs, gx = decode_lanes(lo, na + nb)
+    La, Lb = L // 2, L - L // 2
+    for (base, nv, Ls, nw, off, res) in ((a0, an, La, na, 0, ra),
+                                         (b0, bn, Lb, nb, na, rb)):
+        if nw == 0:
+            assert res["issued_loads"] == 0
+            continue
+        p = oplan.wave_group(Ls, D, nw)
+        assert res["issued_loads"] == p["issued"]
+        ws, wx = checksums.per_lane(words, 16, D, p["Q"], nw, base=base, n_vec=nv)
+        assert np.array_equal(gs[off:off + nw], ws)
+        assert np.array_equal(gx[off:off + nw], wx)
+        assert (res["sum32"], res["xor32"]) == checksums.combine(ws, wx)
+
+
+def test_run_and_batched_equal_single_calls():
+    nbytes = 4 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 1)
+    cells = []
+    for K in (1, 2, 3, 8):
+        cells.append(isw.make_cell(buf, nbytes, K, 16, 8, nbytes // 16))
+    cells.append(isw.make_cell(buf, nbytes, 4, 16, 4, nbytes // 16,
+                               kind=isw.KIND_LDS_ASYNC))
+    cells.append(isw.make_cell(buf, nbytes, 4, 16, 4, nbytes // 16,
+                               kind=isw.KIND_LDS_MATCHED))
+    run = isw.sweep_run(cells)
+    bat, ms = isw.sweep_batched(cells)
+    assert ms > 0
+    words = splitmix.buffer_words(SEED + 1, nbytes)
+    for c, a, b in zip(cells, run, bat):
+        n_waves = a["waves"]
+        p = oplan.wave_group(c.total_logical_loads, c.K, n_waves)
+        want = checksums.combine(*checksums.per_wave(words, 16, c.K, p["Q"], n_waves))
+        assert (a["sum32"], a["xor32"]) == want == (b["sum32"], b["xor32"])
+        assert a["issued_bytes"] == b["issued_bytes"]
+        assert a["gbps"] > 0 and b["gbps"] > 0
+
+
+def _gpu_sum(kind, payload, n, w=8):
+    dt = {"f32": isw.F32, "bf16": isw.BF16, "fp8_e4m3": isw.FP8_E4M3}[kind]
+    return isw.sweep_reduce_fp(payload, n, dt, w)
+
+
+def _oracle_sum(kind, payload_u8):
+    a = payload_u8.cpu().numpy()
+    if kind == "f32":
+        return fpsum.exact_sum(fpsum.decode_f32(a.view(np.uint32)))
+    if kind == "bf16":
+        return fpsum.exact_sum(fpsum.decode_bf16(a.view(np.uint16)))
+    return fpsum.exact_sum_e4m3(a)
+
+
+def _bound(kind, payload_u8, n, res):
+    a = payload_u8.cpu().numpy()
+    x = {"f32": lambda: fpsum.decode_f32(a.view(np.uint32)),
+         "bf16": lambda: fpsum.decode_bf16(a.view(np.uint16)),
+         "fp8_e4m3": lambda: fpsum.decode_e4m3(a)}[kind]()
+    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
+    groups = (n * fpsum_bytes(kind) // 16) // 256
+    g_lane = -(-groups // res["waves"]) if res["waves"] else 0
+    terms = g_lane * (4 * per_vec if kind != "fp8_e4m3" else 1) + per_vec + 16
+    return fpsum.sum2_bound(float(np.abs(x).sum()), terms, 8, res["grid_wgs"])
+
+
+def fpsum_bytes(kind):
+    return {"f32": 4, "bf16": 2, "fp8_e4m3": 1}[kind]
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "fp8_e4m3"])
+@pytest.mark.parametrize("n", [0, 1, 7, 1000, 4096 * 3 + 5, (1 << 20) + 3])
+def test_reduce_matches_exact_sum(kind, n):
+    payload = synth.normal_payload(kind, n, seed=n + 17, device="cuda")
+    pad = torch.zeros(max(16, payload.numel() + 16), dtype=torch.uint8, device="cuda")
+    pad[:payload.numel()] = payload
+    got, res = _gpu_sum(kind, pad, n)
+    want = _oracle_sum(kind, payload)
+    err = abs(got - want)
+    assert err <= _bound(kind, payload, n, res), (got, want)
+
+
+def _negated(u8, kind):
+    """Flip the sign bit of every element of a raw payload."""
+    eb = fpsum_bytes(kind)
+    b = u8.clone().view(-1, eb)
+    b[:, eb - 1] ^= 0x80            # little endian: sign is in the last byte
+    return b.view(-1)
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "fp8_e4m3"])
+def test_reduce_special_cases(kind):
+    n = 64 * 1024 + 5
+    dt = synth.DTYPES[kind]
+    # constant payload: exact n * x
+    x = torch.full((n,), 1.5, dtype=torch.float32, device="cuda").to(dt)
+    got, _ = _gpu_sum(kind, x.view(torch.uint8), n)
+    assert got == n * 1.5
+    # +v / -v pairs cancel exactly
+    v = synth.normal_payload(kind, n, seed=3, device="cuda")
+    both = torch.cat([v, _negated(v, kind)])
+    got, _ = _gpu_sum(kind, both, 2 * n)
+    assert got == 0.0
+
+
+def test_reduce_recovers_absorbed_terms():
+    # every lane meets a large value first: plain FP32 summation would drop
+    # the ones that follow; the compensated sum keeps them exactly
+    n = 1 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    x[: n // 2: 4096] = 2.0**30
+    x[n // 2:: 4096] = -(2.0**30)
+    got, _ = _gpu_sum("f32", x.view(torch.uint8), n)
+    want = _oracle_sum("f32", x.view(torch.uint8))
+    assert got == want
+
+
+def test_fp8_decode_every_finite_code():
+    for code in list(range(0, 0x7F)) + list(range(0x80, 0xFF)):
+        p = torch.full((16,), code, dtype=torch.uint8, device="cuda")
+        got, _ = _gpu_sum("fp8_e4m3", p, 16, w=4)
+        k, _nan = fpsum.e4m3_scaled_int(code)
+        assert got == 16 * k * 2.0**-9, hex(code)
+
+
+def test_host_validation_errors():
+    buf = dev_bytes(1 << 20)
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plain(buf.data_ptr() + 4, (1 << 20) - 1024, 2, 16, 8, 1000)
+    assert e.value.code == isw.EALIGN
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plain(buf, 1 << 20, 0, 16, 8, 1000)
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_lds_async(buf, 1 << 20, 4, 8, 4, 1000)
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_two_stream(buf, 1 << 20, 4, 0, 0, 1000)
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_reduce_fp(buf, 10, 9)
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_fill_u32(buf.data_ptr() + 4, 64, 1)
+    assert e.value.code == isw.EALIGN
