@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Benchmark of the offered-ILP streaming-load path on one MI355X.
+
+One step is one pass of the fixed-work plain-load K sweep: a 1 GiB seeded
+u32 buffer, 16-byte loads, K = 1..16, 2**26 logical loads per cell, at
+1..8 waves per SIMD (4..32 waves per CU), each occupancy swept in ascending
+and then reversed K order (Section 3, "Fixed-work control"; Section 4.2).
+The buffer is resident in HBM before timing starts.  W untimed warm-up
+passes are followed by exactly K timed passes between two device
+synchronisations; the value is the issued bytes of the timed passes over
+their wall time.
+
+After the timed region (untimed, reported beside it):
+  roofline      the plain-load kernel's algorithmic bytes per launch over
+                its mean hipEvent duration, against 8 TB/s, plus the HBM
+                traffic measured by rocprofv3 counters when the committed
+                summary matches the current kernel source
+  cpu_baseline  the CPU oracle computing the per-wave checksums of one
+                full 1 GiB cell of the sweep (bounded sample), checked
+                against the GPU's records of the same cell
+  rows          the other configurations: allocation sweep, LDS-direct vs
+                matched paths, two-stream displacement, autotuned
+                graph-batched sweep, precision sums (--no-extras skips)
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build measures one
+GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PLAIN_SOURCES = ["paper_2608_15764_amd/csrc/kernels_plain.hip",
+                 "paper_2608_15764_amd/csrc/device.hpp"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "plain_kload_1GiB_ksweep_pmc.txt")
+HBM_PEAK_GBPS = 8000.0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in PLAIN_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per plain-load launch from the committed counter summary,
+    or None if there is none or the kernel source changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    kv = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--policy", default="bypass_l1_nt",
+                    choices=["default", "nt", "bypass_l1", "bypass_l1_nt"],
+                    help="cache policy of the swept loads: bypass_l1 is the "
+                         "L1-bypassing analogue of the paper's .cg operator, "
+                         "bypass_l1_nt adds the streaming hint (default)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other configurations")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run plain device copies of 1 GiB (counter scale)")
+    ap.add_argument("--only", default=None,
+                    choices=["c3", "c4", "c5a", "c5b", "c3counters"],
+                    help="run only one extra configuration (no K sweep); "
+                         "c3counters runs the allocation-sweep cells one launch "
+                         "per call for a separate rocprofv3 counter run")
+    ap.add_argument("--manifest", default=None,
+                    help="launch manifest path for --only c3counters")
+    ap.add_argument("--json-out", default=None,
+                    help="also write the full result to this file")
+    return ap.parse_args()
+
+
+def cpu_baseline(buf_seed, nbytes, L, K, waves_per_cu, gpu_buf):
+    """Oracle per-wave checksums of one full cell, timed on the host."""
+    import numpy as np
+    import torch
+    from oracle import checksums, plan as oplan, splitmix
+    from paper_2608_15764_amd import ilpsweep as isw
+
+    rec = torch.zeros(256 * waves_per_cu * 32, dtype=torch.uint8, device="cuda")
+    r = isw.sweep_plain(gpu_buf, nbytes, K, 16, waves_per_cu, L,
+                        isw.make_opts(wave_out=rec))
+    dt = np.dtype([("sum32", "<u4"), ("xor32", "<u4"), ("hw_id", "<u4"),
+                   ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
+    recs = rec.cpu().numpy().view(dt)[: r["waves"]]
+    t0 = time.perf_counter()
+    words = splitmix.buffer_words(buf_seed, nbytes)
+    t1 = time.perf_counter()
+    p = oplan.wave_group(L, K, r["waves"])
+    s, x = checksums.per_wave(words, 16, K, p["Q"], r["waves"])
+    t2 = time.perf_counter()
+    ok = bool(np.array_equal(s, recs["sum32"]) and np.array_equal(x, recs["xor32"])
+              and p["issued"] == r["issued_loads"])
+    return {
+        "value": p["issued"] * 16 / (t2 - t1) / 1e9,
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one full cell of the sweep: per-wave sum/xor checksums of "
+                   f"{p['issued'] * 16 >> 20} MiB issued (K={K}, "
+                   f"{waves_per_cu} waves/CU, {r['waves']} waves), NumPy, one "
+                   f"process; buffer generation {t1 - t0:.1f} s excluded"),
+        "checksum_s": t2 - t1,
+        "generate_s": t1 - t0,
+        "host_cores_available": os.cpu_count(),
+        "matches_gpu": ok,
+    }
+
+
+def main():
+    a = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the path is single-GPU (each GPU would "
+              "stream its own HBM; see the sharding note in DESIGN.md); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2608_15764_amd import ilpsweep as isw
+    from paper_2608_15764_amd import stats, sweeps
+
+    torch.cuda.set_device(0)
+    info = isw.sweep_device_info()
+    hz = isw.sweep_calibrate_clock(0.5)
+    policy = isw.POLICY_NAMES[a.policy]
+    out_extra = {}
+
+    if a.only == "c3counters":
+        GIB = 1 << 30
+        sizes = [512 << 20, GIB, 2 * GIB, 4 * GIB, 8 * GIB, 20 * GIB]
+        man = sweeps.allocation_counter_pass(sizes, policy=policy, manifest=a.manifest)
+        print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only:
+        out_extra = run_extras(a, isw, sweeps, only=a.only)
+        print(json.dumps({"only": a.only, "rows": out_extra}, default=str))
+        return 0
+
+    nbytes, L = 1 << 30, 1 << 26
+    seed = sweeps.SEED_BASE + 1
+    buf = sweeps.device_buffer(nbytes, seed)
+    waves_list = [4 * w for w in range(1, 9)]
+    Ks = list(range(1, 17))
+    cells, meta = sweeps.plain_k_cells(buf, nbytes, L, policy, waves_list, Ks)
+    cells, meta, dropped = sweeps.drop_infeasible(cells, meta)
+
+    arr = isw.cell_array(cells)
+    for _ in range(a.warmup):
+        isw.sweep_run(arr, raw=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    raws = [isw.sweep_run(arr, raw=True) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    runs = [isw.result_dicts(r) for r in raws]
+
+    step_bytes = sum(r["issued_bytes"] for r in runs[0])
+    value = a.steps * step_bytes / (t1 - t0) / 1e9
+    kernel_ms = sum(r["event_ms"] for run in runs for r in run)
+    launches = sum(len(run) for run in runs)
+    achieved = a.steps * step_bytes / (kernel_ms * 1e6)
+    traffic = traffic_from_profile()
+    summ = sweeps.summarize_k_sweep(meta, runs)
+    best_w = summ["best_waves_per_cu"]
+    cb = summ["curves"][best_w]
+    w4 = summ["curves"].get(16)
+
+    if a.calib_copy:
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    result = {
+        "metric": "attained HBM GB/s vs offered loads/thread K; % of HBM peak; K=2->8 decline %",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round((t1 - t0) / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (SplitMix64-seeded uint32 buffer, resident in HBM)",
+        "config": {
+            "workload": ("fixed-work plain-load K sweep: 1 GiB seeded u32 buffer, "
+                         "16-byte loads, K=1..16, 2^26 logical loads per cell, "
+                         "1..8 waves/SIMD, ascending then reversed K"),
+            "buffer_bytes": nbytes, "vec_width": 16, "L": L, "Ks": Ks,
+            "waves_per_cu": waves_list, "orders": ["asc", "rev"],
+            "cache_policy": a.policy, "cells_per_step": len(cells),
+            "infeasible_cells": dropped,
+        },
+        "curve_peak_gbps": round(summ["peak_gbps"], 1),
+        "curve_peak_frac_of_hbm": round(summ["peak_gbps"] / HBM_PEAK_GBPS, 4),
+        "best_waves_per_cu": best_w,
+        "peak_K_at_best": cb["peak_K"],
+        "decline_2_8_at_best": cb.get("decline_2_8"),
+        "paper_like_cell": None if w4 is None else {
+            "waves_per_cu": 16, "median_gbps": w4["median_gbps"],
+            "peak_K": w4["peak_K"], "decline_2_8": w4.get("decline_2_8"),
+            "regime": w4["regime"], "by_order": w4["by_order"]},
+        "curves": {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                       "peak_K": c["peak_K"], "knee_K": c["knee_K"],
+                       "regime": c["regime"], "decline_2_8": c.get("decline_2_8"),
+                       "by_order": c["by_order"]}
+                   for w, c in summ["curves"].items()},
+        "kset_mismatch": summ["kset_mismatch"],
+        "checksums_consistent": summ["checksums_consistent"],
+        "residency_flags": summ["residency_flags"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "ilp::plain_kload<K,16,policy>",
+                     "launches": launches,
+                     "mean_launch_us": round(kernel_ms / launches * 1e3, 2),
+                     "algorithmic_bytes_per_launch": step_bytes // len(cells)},
+        "device": {"arch": info["arch"], "cus": info["num_cus"],
+                   "clock_hz_calibrated": hz},
+    }
+    if not a.no_extras:
+        # one untimed pass of the same sweep under every cache policy
+        pc = {}
+        for name, pol in isw.POLICY_NAMES.items():
+            pcells, pmeta = sweeps.plain_k_cells(buf, nbytes, L, pol, waves_list, Ks)
+            pcells, pmeta, _ = sweeps.drop_infeasible(pcells, pmeta)
+            s2 = sweeps.summarize_k_sweep(pmeta, [isw.sweep_run(pcells)])
+            c16 = s2["curves"].get(16, {})
+            pc[name] = {"peak_gbps": round(s2["peak_gbps"], 1),
+                        "best_waves_per_cu": s2["best_waves_per_cu"],
+                        "paper_like_decline_2_8": c16.get("decline_2_8"),
+                        "paper_like_median_gbps": {k: round(v, 1) for k, v in
+                                                   c16.get("median_gbps", {}).items()}}
+        result["policy_curves"] = pc
+    if not a.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, 2, best_w, buf)
+    del buf
+    torch.cuda.empty_cache()
+    if not a.no_extras:
+        result["rows"] = run_extras(a, isw, sweeps)
+    line = json.dumps(result, default=str)
+    if a.json_out:
+        with open(a.json_out, "w") as f:
+            f.write(line + "\n")
+    print(line, flush=True)
+    return 0
+
+
+def run_extras(a, isw, sweeps, only=None):
+    import torch
+    rows = {}
+    GIB = 1 << 30
+    if only in (None, "c3"):
+        t = time.perf_counter()
+        sizes = [512 << 20, GIB, 2 * GIB, 4 * GIB, 8 * GIB, 20 * GIB]
+        rows["c3_allocation_sweep"] = sweeps.allocation_sweep(
+            sizes, waves_list=(16, 32), policy=isw.POLICY_NAMES[a.policy])
+        rows["c3_allocation_sweep"]["wall_s"] = time.perf_counter() - t
+    if only in (None, "c4"):
+        t = time.perf_counter()
+        nbytes = 2 * GIB
+        buf = sweeps.device_buffer(nbytes, sweeps.SEED_BASE + 3)
+        L = nbytes // 16
+        rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L)
+        rows["c4_two_stream"] = sweeps.two_stream(buf, nbytes, L)
+        rows["c4_wall_s"] = time.perf_counter() - t
+        del buf
+        torch.cuda.empty_cache()
+    if only in (None, "c5a"):
+        t = time.perf_counter()
+        rows["c5a_batched"] = sweeps.batched_autotuned()
+        rows["c5a_batched"]["wall_s"] = time.perf_counter() - t
+    if only in (None, "c5b"):
+        t = time.perf_counter()
+        rows["c5b_precision"] = sweeps.precision_sum()
+        rows["c5b_precision"]["wall_s"] = time.perf_counter() - t
+    return rows
+
+
+if __name__ == "__main__":
+    sys.exit(main())

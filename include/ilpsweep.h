@@ -71,6 +71,8 @@ extern "C" {
 #define SWEEP_CACHE_NT        1  /* global_load ... nt (streaming hint)        */
 #define SWEEP_CACHE_BYPASS_L1 2  /* buffer_load ... sc1: device scope, misses
                                     the vector L1 (the analogue of .cg)        */
+#define SWEEP_CACHE_BYPASS_L1_NT 3 /* buffer_load ... sc1 nt: L1 bypass plus the
+                                    streaming (non-temporal) hint              */
 
 /* ----------------------------------------------------------------- kinds */
 #define SWEEP_KIND_PLAIN        0  /* K independent loads into registers      */

@@ -85,13 +85,20 @@ def exact_sum(values, chunk=1 << 22):
 
 
 def exact_sum_rational(values, chunk=1 << 22):
-    """Exact sum of a float array as a Fraction (see module docstring)."""
-    x = np.asarray(values, dtype=np.float64).ravel()
+    """Exact sum of a float array as a Fraction (see module docstring).
+
+    The input is widened to binary64 chunk by chunk (exactly), so a large
+    binary32 payload is never copied whole.
+    """
+    x = np.asarray(values).ravel()
     if x.size == 0:
         return Fraction(0)
-    if not np.all(np.isfinite(x)):
-        raise ValueError("payload holds a non-finite value")
-    amax = float(np.max(np.abs(x)))
+    amax = 0.0
+    for s in range(0, x.size, chunk):
+        c = x[s:s + chunk].astype(np.float64)
+        if not np.all(np.isfinite(c)):
+            raise ValueError("payload holds a non-finite value")
+        amax = max(amax, float(np.max(np.abs(c))))
     if amax == 0.0:
         return Fraction(0)
     # |x| < 2**e_max, so |x * 2**P| < 2**51 with P = 51 - e_max
@@ -100,7 +107,7 @@ def exact_sum_rational(values, chunk=1 << 22):
     hi_total = 0
     rem = []
     for s in range(0, x.size, chunk):
-        a = np.ldexp(x[s:s + chunk], P)            # exact scaling
+        a = np.ldexp(x[s:s + chunk].astype(np.float64), P)   # exact scaling
         h = np.trunc(a)
         r = a - h                                  # exact fractional part
         hi = h.astype(np.int64)

@@ -1,7 +1,7 @@
 // Device-side building blocks shared by the gfx950 sweep kernels.
 //
 //  - 4/8/16-byte vector loads of one coalesced 64-lane segment under the
-//    three cache policies of the C ABI,
+//    four cache policies of the C ABI,
 //  - the per-lane sinks (wrapping 32-bit sum and XOR of every loaded word,
 //    the non-eliminable sink of Section 3, "Instruments"),
 //  - DPP wave reductions of the sinks,
@@ -27,9 +27,11 @@ constexpr int kWave = 64;
 // Buffer-resource word 3 for gfx9-family raw (untyped) buffer loads:
 // DATA_FORMAT = 32-bit, everything else zero.
 constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kNumPolicies = 4;
 // Cache-policy bits of the gfx940-family MUBUF/global encodings as taken by
 // the buffer-load builtins' aux operand: sc0 = 1, nt = 2, sc1 = 16.
 constexpr int kAuxSc1 = 16;
+constexpr int kAuxSc1Nt = 16 | 2;
 
 // --------------------------------------------------------------- identities
 __device__ __forceinline__ uint32_t wave_in_wg() {
@@ -62,14 +64,16 @@ __device__ __forceinline__ typename Vec<V>::T load_seg(const uint8_t* seg,
   } else if constexpr (POL == SWEEP_CACHE_NT) {
     return __builtin_nontemporal_load(reinterpret_cast<const T*>(seg + lane * V));
   } else {
+    // buffer load over exactly this segment (out-of-range lanes would read 0)
+    constexpr int aux = POL == SWEEP_CACHE_BYPASS_L1 ? kAuxSc1 : kAuxSc1Nt;
     __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(seg), 0, kWave * V, kRsrcWord3);
     if constexpr (V == 4) {
-      return __builtin_amdgcn_raw_buffer_load_b32(r, lane * V, 0, kAuxSc1);
+      return __builtin_amdgcn_raw_buffer_load_b32(r, lane * V, 0, aux);
     } else if constexpr (V == 8) {
-      return __builtin_amdgcn_raw_buffer_load_b64(r, lane * V, 0, kAuxSc1);
+      return __builtin_amdgcn_raw_buffer_load_b64(r, lane * V, 0, aux);
     } else {
-      return __builtin_amdgcn_raw_buffer_load_b128(r, lane * V, 0, kAuxSc1);
+      return __builtin_amdgcn_raw_buffer_load_b128(r, lane * V, 0, aux);
     }
   }
 }

@@ -86,8 +86,9 @@ hipError_t launch_two_stream(int D, int policy, uint32_t grid,
 // ---- fill, finishing, clock, reduction (kernels_misc.hip)
 hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,
                        hipStream_t st);
-hipError_t launch_finish(const sweep_wave_rec_t* rec, uint32_t n_waves,
-                         CellRes* out, hipStream_t st);
+// One workgroup per cell: cell c owns records [offsets[c], offsets[c+1]).
+hipError_t launch_finish_cells(const sweep_wave_rec_t* rec, const uint64_t* offsets,
+                               uint32_t n_cells, CellRes* out, hipStream_t st);
 hipError_t launch_read_clock(uint64_t* out, hipStream_t st);
 const void* reduce_kernel(int dtype);
 hipError_t launch_reduce(int dtype, uint32_t grid, hipStream_t st,

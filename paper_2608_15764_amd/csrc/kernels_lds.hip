@@ -84,13 +84,13 @@ constexpr auto kTwoRow = two_row<POL>(std::make_integer_sequence<int, kMaxK>{});
 }  // namespace
 
 const void* lds_kernel(int kind, int D, int policy) {
-  static const std::array<LdsFn, kMaxK> t[2][3] = {
+  static const std::array<LdsFn, kMaxK> t[2][kNumPolicies] = {
       {kLdsRow<SWEEP_KIND_LDS_ASYNC, 0>, kLdsRow<SWEEP_KIND_LDS_ASYNC, 1>,
-       kLdsRow<SWEEP_KIND_LDS_ASYNC, 2>},
+       kLdsRow<SWEEP_KIND_LDS_ASYNC, 2>, kLdsRow<SWEEP_KIND_LDS_ASYNC, 3>},
       {kLdsRow<SWEEP_KIND_LDS_MATCHED, 0>, kLdsRow<SWEEP_KIND_LDS_MATCHED, 1>,
-       kLdsRow<SWEEP_KIND_LDS_MATCHED, 2>},
+       kLdsRow<SWEEP_KIND_LDS_MATCHED, 2>, kLdsRow<SWEEP_KIND_LDS_MATCHED, 3>},
   };
-  if (D < 1 || D > kMaxK || policy < 0 || policy > 2) return nullptr;
+  if (D < 1 || D > kMaxK || policy < 0 || policy >= kNumPolicies) return nullptr;
   if (kind == SWEEP_KIND_LDS_ASYNC) return reinterpret_cast<const void*>(t[0][policy][D - 1]);
   if (kind == SWEEP_KIND_LDS_MATCHED) return reinterpret_cast<const void*>(t[1][policy][D - 1]);
   return nullptr;
@@ -106,8 +106,9 @@ hipError_t launch_lds(int kind, int D, int policy, uint32_t grid,
 }
 
 const void* two_stream_kernel(int D, int policy) {
-  static const std::array<TwoFn, kMaxK> t[3] = {kTwoRow<0>, kTwoRow<1>, kTwoRow<2>};
-  if (D < 1 || D > kMaxK || policy < 0 || policy > 2) return nullptr;
+  static const std::array<TwoFn, kMaxK> t[kNumPolicies] = {kTwoRow<0>, kTwoRow<1>,
+                                                           kTwoRow<2>, kTwoRow<3>};
+  if (D < 1 || D > kMaxK || policy < 0 || policy >= kNumPolicies) return nullptr;
   return reinterpret_cast<const void*>(t[policy][D - 1]);
 }
 

@@ -46,15 +46,18 @@ hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,
 }
 
 // ---------------------------------------------------------------- finish
-// One workgroup folds the wave records of a cell into its global sinks and
-// its clock window [min t0, max t1].
-__global__ __launch_bounds__(256) void finish_cell(const sweep_wave_rec_t* rec,
-                                                   uint32_t n, CellRes* out) {
+// Workgroup c folds the wave records of cell c, rec[offsets[c] ..
+// offsets[c+1]), into the cell's global sinks and its clock window
+// [min t0, max t1].
+__global__ __launch_bounds__(256) void finish_cells(const sweep_wave_rec_t* rec,
+                                                    const uint64_t* offsets,
+                                                    CellRes* out) {
   __shared__ uint32_t ss[256], sx[256];
   __shared__ uint64_t smin[256], smax[256];
+  const uint64_t lo_i = offsets[blockIdx.x], hi_i = offsets[blockIdx.x + 1];
   uint32_t s = 0, x = 0;
   uint64_t lo = ~0ull, hi = 0;
-  for (uint32_t i = threadIdx.x; i < n; i += 256) {
+  for (uint64_t i = lo_i + threadIdx.x; i < hi_i; i += 256) {
     const sweep_wave_rec_t r = rec[i];
     s += r.sum32;
     x ^= r.xor32;
@@ -81,13 +84,13 @@ __global__ __launch_bounds__(256) void finish_cell(const sweep_wave_rec_t* rec,
     r.xr = sx[0];
     r.tmin = smin[0];
     r.tmax = smax[0];
-    *out = r;
+    out[blockIdx.x] = r;
   }
 }
 
-hipError_t launch_finish(const sweep_wave_rec_t* rec, uint32_t n_waves,
-                         CellRes* out, hipStream_t st) {
-  hipLaunchKernelGGL(finish_cell, dim3(1), dim3(256), 0, st, rec, n_waves, out);
+hipError_t launch_finish_cells(const sweep_wave_rec_t* rec, const uint64_t* offsets,
+                               uint32_t n_cells, CellRes* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_cells, dim3(n_cells), dim3(256), 0, st, rec, offsets, out);
   return hipGetLastError();
 }
 
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void reduce_fp(ReduceArgs a) {
     u32x4 v[kRedLoads];
 #pragma unroll
     for (int j = 0; j < kRedLoads; ++j)
-      v[j] = load_seg<16, SWEEP_CACHE_DEFAULT>(base + j * (kWave * 16), lane);
+      v[j] = load_seg<16, SWEEP_CACHE_NT>(base + j * (kWave * 16), lane);
     if constexpr (DT == SWEEP_FP8_E4M3) {
       // 64 e4m3 values are k * 2^-9 with |k| <= 64 * 229376 < 2^24, so
       // their FP32 sum is exact; one TwoSum per 64 values

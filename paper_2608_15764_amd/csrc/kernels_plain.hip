@@ -35,6 +35,9 @@ __global__ __launch_bounds__(kPlainWgThreads) void plain_kload(PlainArgs a) {
       pj += kWave;
       if (pj >= a.n_vec) pj -= a.n_vec;
     }
+    // all K loads are issued before the first is consumed: without this
+    // barrier the scheduler may refill registers early to raise occupancy
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < K; ++j) fold(v[j], s, x);
     p += a.stride;
@@ -58,10 +61,10 @@ constexpr auto kRow = row<V, POL>(std::make_integer_sequence<int, kMaxK>{});
 
 // [vector width index][policy][K-1]
 const PlainFn* table(int vi, int pol) {
-  static const std::array<PlainFn, kMaxK> t[3][3] = {
-      {kRow<4, 0>, kRow<4, 1>, kRow<4, 2>},
-      {kRow<8, 0>, kRow<8, 1>, kRow<8, 2>},
-      {kRow<16, 0>, kRow<16, 1>, kRow<16, 2>},
+  static const std::array<PlainFn, kMaxK> t[3][kNumPolicies] = {
+      {kRow<4, 0>, kRow<4, 1>, kRow<4, 2>, kRow<4, 3>},
+      {kRow<8, 0>, kRow<8, 1>, kRow<8, 2>, kRow<8, 3>},
+      {kRow<16, 0>, kRow<16, 1>, kRow<16, 2>, kRow<16, 3>},
   };
   return t[vi][pol].data();
 }
@@ -72,7 +75,7 @@ int width_index(int V) { return V == 4 ? 0 : V == 8 ? 1 : V == 16 ? 2 : -1; }
 
 const void* plain_kernel(int K, int V, int policy) {
   const int vi = width_index(V);
-  if (vi < 0 || K < 1 || K > kMaxK || policy < 0 || policy > 2) return nullptr;
+  if (vi < 0 || K < 1 || K > kMaxK || policy < 0 || policy >= kNumPolicies) return nullptr;
   return reinterpret_cast<const void*>(table(vi, policy)[K - 1]);
 }
 

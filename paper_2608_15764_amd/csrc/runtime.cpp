@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "ilpsweep.h"
@@ -60,8 +61,18 @@ struct Dev {
   double* dsum = nullptr;
   double* dsum_h = nullptr;
   uint64_t* clk = nullptr;
+  uint64_t* offs = nullptr;     // per-cell record offsets (device)
+  size_t offs_cap = 0;
+  uint64_t* offs_h = nullptr;   // pinned staging copy
+  size_t offs_h_cap = 0;
   std::vector<hipEvent_t> ev;
   hipStream_t capture = nullptr;
+  // kernel attributes and residency limit per (kernel, WG threads, LDS)
+  struct Occ {
+    hipFuncAttributes fa;
+    int max_wgs;
+  };
+  std::map<std::tuple<const void*, uint32_t, size_t>, Occ> occ;
   double hz() const { return cal_hz > 0 ? cal_hz : nominal_hz; }
 };
 
@@ -162,7 +173,7 @@ struct Prepared {
   hipFuncAttributes fa{};
 };
 
-int prepare(const Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
+int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   PlanIn in;
   in.bytes = c.bytes;
   in.K = c.K;
@@ -184,7 +195,7 @@ int prepare(const Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   if (c.buf == nullptr) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
   if (reinterpret_cast<uintptr_t>(c.buf) % 16)
     return fail(SWEEP_EALIGN, "buffer must be 16-byte aligned");
-  if (c.cache_policy < 0 || c.cache_policy > 2)
+  if (c.cache_policy < 0 || c.cache_policy > 3)
     return fail(SWEEP_EINVAL, "unknown cache policy");
   p.fn = c.kind == SWEEP_KIND_PLAIN ? plain_kernel(c.K, c.vec_width, c.cache_policy)
                                     : lds_kernel(c.kind, c.K, c.cache_policy);
@@ -193,9 +204,17 @@ int prepare(const Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   p.threads = p.plan.pub.wg_threads;
   p.lds = p.plan.lds_ring_bytes;
   if (pin && p.plan.pub.lds_pad_bytes > p.lds) p.lds = p.plan.pub.lds_pad_bytes;
-  HIP_TRY(hipFuncGetAttributes(&p.fa, p.fn));
-  int nb = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p.fn, (int)p.threads, p.lds));
+  const auto key = std::make_tuple(p.fn, p.threads, p.lds);
+  auto it = d.occ.find(key);
+  if (it == d.occ.end()) {
+    Dev::Occ o;
+    HIP_TRY(hipFuncGetAttributes(&o.fa, p.fn));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o.max_wgs, p.fn, (int)p.threads,
+                                                         p.lds));
+    it = d.occ.emplace(key, o).first;
+  }
+  p.fa = it->second.fa;
+  const int nb = it->second.max_wgs;
   p.max_wgs = nb;
   if ((uint32_t)nb < p.plan.wgs_per_cu)
     return fail(SWEEP_EOCCUPANCY,
@@ -207,8 +226,10 @@ int prepare(const Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   return SWEEP_OK;
 }
 
+// Records the optional events around the cell's kernel; the wave records
+// go to `rec`, which holds at least the cell's waves.
 hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
-                   uint32_t* lane_out, CellRes* slot, hipEvent_t e0, hipEvent_t e1) {
+                   uint32_t* lane_out, hipEvent_t e0, hipEvent_t e1) {
   hipError_t e = hipSuccess;
   if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
   if (p.c.kind == SWEEP_KIND_PLAIN) {
@@ -222,7 +243,23 @@ hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
   }
   if (e != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
-  return launch_finish(rec, p.plan.pub.waves, slot, st);
+  return hipSuccess;
+}
+
+// Copies the record offsets of `n` cells (n + 1 entries) to the device.
+int upload_offsets(Dev& d, const std::vector<uint64_t>& offs, hipStream_t st) {
+  SW_TRY(ensure_host(d.offs_h, d.offs_h_cap, offs.size()));
+  SW_TRY(ensure_dev(d.offs, d.offs_cap, offs.size()));
+  std::copy(offs.begin(), offs.end(), d.offs_h);
+  HIP_TRY(hipMemcpyAsync(d.offs, d.offs_h, offs.size() * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, st));
+  return SWEEP_OK;
+}
+
+std::vector<uint64_t> record_offsets(const std::vector<Prepared>& ps) {
+  std::vector<uint64_t> o(ps.size() + 1, 0);
+  for (size_t i = 0; i < ps.size(); ++i) o[i + 1] = o[i] + ps[i].plan.pub.waves;
+  return o;
 }
 
 void fill_result(const Dev& d, const Prepared& p, const CellRes& r, double ms,
@@ -276,21 +313,23 @@ sweep_cell_t cell_from(int kind, const void* buf, size_t bytes, int K, int V,
 
 int pin_of(const sweep_opts_t* o) { return o ? o->pin_occupancy : 1; }
 
-// Runs prepared cells back to back; one synchronisation at the end.
+// Runs prepared cells back to back, each writing its own record region,
+// then one finishing kernel for all cells; one synchronisation at the end.
 int run_prepared(Dev& d, std::vector<Prepared>& ps, hipStream_t st,
                  sweep_wave_rec_t* wave_out, uint32_t* lane_out,
                  sweep_result_t* results) {
   const size_t n = ps.size();
-  size_t max_waves = 0;
-  for (auto& p : ps) max_waves = std::max<size_t>(max_waves, p.plan.pub.waves);
-  SW_TRY(ensure_dev(d.rec, d.rec_cap, max_waves));
+  const std::vector<uint64_t> offs = record_offsets(ps);
+  if (!wave_out) SW_TRY(ensure_dev(d.rec, d.rec_cap, offs[n]));
   SW_TRY(ensure_dev(d.res, d.res_cap, n));
   SW_TRY(ensure_host(d.res_h, d.res_h_cap, n));
   SW_TRY(ensure_events(d, 2 * n + 1));
-  for (size_t i = 0; i < n; ++i) {
-    sweep_wave_rec_t* rec = wave_out ? wave_out : d.rec;
-    HIP_TRY(enqueue(ps[i], st, rec, lane_out, d.res + i, d.ev[2 * i], d.ev[2 * i + 1]));
-  }
+  sweep_wave_rec_t* rec = wave_out ? wave_out : d.rec;
+  if (wave_out && n != 1) return fail(SWEEP_EINVAL, "wave_out takes a single cell");
+  SW_TRY(upload_offsets(d, offs, st));
+  for (size_t i = 0; i < n; ++i)
+    HIP_TRY(enqueue(ps[i], st, rec + offs[i], lane_out, d.ev[2 * i], d.ev[2 * i + 1]));
+  HIP_TRY(launch_finish_cells(rec, d.offs, (uint32_t)n, d.res, st));
   HIP_TRY(hipMemcpyAsync(d.res_h, d.res, n * sizeof(CellRes), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(d.ev[2 * n], st));
   HIP_TRY(hipEventSynchronize(d.ev[2 * n]));
@@ -345,6 +384,8 @@ int sweep_shutdown(void) {
     if (d->dsum) (void)hipFree(d->dsum);
     if (d->dsum_h) (void)hipHostFree(d->dsum_h);
     if (d->clk) (void)hipFree(d->clk);
+    if (d->offs) (void)hipFree(d->offs);
+    if (d->offs_h) (void)hipHostFree(d->offs_h);
     for (auto e : d->ev) (void)hipEventDestroy(e);
     if (d->capture) (void)hipStreamDestroy(d->capture);
     delete d;
@@ -487,7 +528,7 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
     return fail(SWEEP_EALIGN, "two-stream needs a 16-byte aligned buffer, bytes % 2048 == 0");
   if (total_logical_loads == 0) return fail(SWEEP_EINVAL, "total_logical_loads is 0");
   const int pol = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
-  if (pol < 0 || pol > 2) return fail(SWEEP_EINVAL, "unknown cache policy");
+  if (pol < 0 || pol > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
   std::lock_guard<std::mutex> lk(g_mu);
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
@@ -524,11 +565,11 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
   a.rec = rec;
   a.lane_out = opt ? opt->lane_out : nullptr;
   hipStream_t st = as_stream(opt);
+  SW_TRY(upload_offsets(*d, {0ull, (uint64_t)wa, (uint64_t)wa + wb}, st));
   HIP_TRY(hipEventRecord(d->ev[0], st));
   HIP_TRY(launch_two_stream(depth, pol, grid, threads, lds, st, a));
   HIP_TRY(hipEventRecord(d->ev[1], st));
-  HIP_TRY(launch_finish(rec, wa, d->res, st));
-  HIP_TRY(launch_finish(rec + wa, wb, d->res + 1, st));
+  HIP_TRY(launch_finish_cells(rec, d->offs, 2, d->res, st));
   HIP_TRY(hipMemcpyAsync(d->res_h, d->res, 2 * sizeof(CellRes), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(d->ev[2], st));
   HIP_TRY(hipEventSynchronize(d->ev[2]));
@@ -585,21 +626,25 @@ int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
   std::vector<Prepared> ps((size_t)n);
-  size_t max_waves = 0;
-  for (int i = 0; i < n; ++i) {
-    SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
-    max_waves = std::max<size_t>(max_waves, ps[(size_t)i].plan.pub.waves);
-  }
-  SW_TRY(ensure_dev(d->rec, d->rec_cap, max_waves));
+  for (int i = 0; i < n; ++i) SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
+  const std::vector<uint64_t> offs = record_offsets(ps);
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, offs[(size_t)n]));
   SW_TRY(ensure_dev(d->res, d->res_cap, (size_t)n));
   SW_TRY(ensure_host(d->res_h, d->res_h_cap, (size_t)n));
   SW_TRY(ensure_events(*d, 3));
+  hipStream_t st = as_stream(opt);
+  // the offsets are uploaded before capture: the graph holds kernels only
+  SW_TRY(upload_offsets(*d, offs, st));
+  HIP_TRY(hipStreamSynchronize(st));
   if (!d->capture) HIP_TRY(hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
   hipError_t cap_err = hipSuccess;
   for (int i = 0; i < n && cap_err == hipSuccess; ++i)
-    cap_err = enqueue(ps[(size_t)i], d->capture, d->rec, nullptr, d->res + i, nullptr, nullptr);
+    cap_err = enqueue(ps[(size_t)i], d->capture, d->rec + offs[(size_t)i], nullptr,
+                      nullptr, nullptr);
+  if (cap_err == hipSuccess)
+    cap_err = launch_finish_cells(d->rec, d->offs, (uint32_t)n, d->res, d->capture);
   hipError_t end_err = hipStreamEndCapture(d->capture, &graph);
   if (cap_err != hipSuccess || end_err != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -612,7 +657,6 @@ int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
     (void)hipGraphDestroy(graph);
     return fail(SWEEP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
   }
-  hipStream_t st = as_stream(opt);
   hipError_t le = hipEventRecord(d->ev[0], st);
   if (le == hipSuccess) le = hipGraphLaunch(exec, st);
   if (le == hipSuccess) le = hipEventRecord(d->ev[1], st);
@@ -720,11 +764,12 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
   a.partials = d->partials;
   a.rec = d->rec;
   hipStream_t st = as_stream(opt);
+  SW_TRY(upload_offsets(*d, {0ull, (uint64_t)grid * 4}, st));
   HIP_TRY(hipEventRecord(d->ev[0], st));
   HIP_TRY(launch_reduce(dtype, grid, st, a));
   HIP_TRY(hipEventRecord(d->ev[1], st));
   HIP_TRY(launch_reduce_finish(d->partials, grid, d->dsum, st));
-  HIP_TRY(launch_finish(d->rec, grid * 4, d->res, st));
+  HIP_TRY(launch_finish_cells(d->rec, d->offs, 1, d->res, st));
   HIP_TRY(hipMemcpyAsync(d->dsum_h, d->dsum, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(d->res_h, d->res, sizeof(CellRes), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(d->ev[2], st));

@@ -33,7 +33,7 @@ __device__ __forceinline__ uint64_t groups_of(uint64_t wid, uint64_t Q,
 
 // One 16-byte-per-lane LDS-direct request: lane l's bytes land in
 // slot[l] (global_load_lds_dwordx4 writes LDS at M0 + 16*lane).  The last
-// builtin operand is the cache policy: 0, nt (2) or sc1 (16).
+// builtin operand is the cache policy: 0, nt (2), sc1 (16) or sc1 nt (18).
 template <int POL>
 __device__ __forceinline__ void lds_issue(const uint8_t* seg, u32x4* slot,
                                           uint32_t lane) {
@@ -43,8 +43,10 @@ __device__ __forceinline__ void lds_issue(const uint8_t* seg, u32x4* slot,
     __builtin_amdgcn_global_load_lds(seg + lane * 16, dst, 16, 0, 0);
   } else if constexpr (POL == SWEEP_CACHE_NT) {
     __builtin_amdgcn_global_load_lds(seg + lane * 16, dst, 16, 0, 2);
-  } else {
+  } else if constexpr (POL == SWEEP_CACHE_BYPASS_L1) {
     __builtin_amdgcn_global_load_lds(seg + lane * 16, dst, 16, 0, 16);
+  } else {
+    __builtin_amdgcn_global_load_lds(seg + lane * 16, dst, 16, 0, 18);
   }
 }
 
@@ -65,6 +67,7 @@ __device__ __forceinline__ void plain_loop16(const uint8_t* buf, uint64_t n_vec,
       v[j] = load_seg<16, POL>(buf + pj * 16, lane);
       pj = wrap_add(pj, kWave, n_vec);
     }
+    __builtin_amdgcn_sched_barrier(0);   // all K issued before any fold
 #pragma unroll
     for (int j = 0; j < K; ++j) fold(v[j], s, x);
     p = wrap_add(p, stride, n_vec);

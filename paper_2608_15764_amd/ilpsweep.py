@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
 # ---------------------------------------------------------------- constants
 OK, EINVAL, EALIGN, EOCCUPANCY, EHIP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6
 FIXED_WORK, FIXED_ITERS, PER_THREAD_FLOOR = 0, 1, 2
-CACHE_DEFAULT, CACHE_NT, CACHE_BYPASS_L1 = 0, 1, 2
+CACHE_DEFAULT, CACHE_NT, CACHE_BYPASS_L1, CACHE_BYPASS_L1_NT = 0, 1, 2, 3
+POLICY_NAMES = {"default": 0, "nt": 1, "bypass_l1": 2, "bypass_l1_nt": 3}
 KIND_PLAIN, KIND_LDS_ASYNC, KIND_LDS_MATCHED = 0, 1, 2
 F32, BF16, FP8_E4M3 = 0, 1, 2
 
@@ -278,29 +279,39 @@ def make_cell(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
     return c
 
 
-def _cells(cells):
+def cell_array(cells):
+    """A ctypes array of cells (build once, pass to sweep_run repeatedly)."""
+    if isinstance(cells, C.Array):
+        return cells
     arr = (sweep_cell_t * len(cells))()
     for i, c in enumerate(cells):
         arr[i] = c if isinstance(c, sweep_cell_t) else make_cell(**c)
     return arr
 
 
-def sweep_run(cells, opts=None):
-    arr = _cells(cells)
-    res = (sweep_result_t * len(cells))()
+def result_dicts(raw):
+    """Convert a ctypes result array into a list of dicts."""
+    return [r.as_dict() for r in raw]
+
+
+def sweep_run(cells, opts=None, raw=False):
+    """Run cells back to back.  ``raw=True`` returns the ctypes result array
+    (convert with :func:`result_dicts`), keeping conversion out of timing."""
+    arr = cell_array(cells)
+    res = (sweep_result_t * len(arr))()
     o = opts if opts is not None else make_opts()
-    _check(lib.sweep_run(arr, len(cells), C.byref(o), res), "sweep_run")
-    return [r.as_dict() for r in res]
+    _check(lib.sweep_run(arr, len(arr), C.byref(o), res), "sweep_run")
+    return res if raw else result_dicts(res)
 
 
-def sweep_batched(cells, opts=None):
-    arr = _cells(cells)
-    res = (sweep_result_t * len(cells))()
+def sweep_batched(cells, opts=None, raw=False):
+    arr = cell_array(cells)
+    res = (sweep_result_t * len(arr))()
     o = opts if opts is not None else make_opts()
     ms = C.c_double()
-    _check(lib.sweep_batched(arr, len(cells), C.byref(o), res, C.byref(ms)),
+    _check(lib.sweep_batched(arr, len(arr), C.byref(o), res, C.byref(ms)),
            "sweep_batched")
-    return [r.as_dict() for r in res], ms.value
+    return (res if raw else result_dicts(res)), ms.value
 
 
 def sweep_autotune(buf, bytes_, vec_widths, Ks, waves_per_cu,

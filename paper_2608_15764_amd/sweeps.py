@@ -1,0 +1,404 @@
+"""Sweep drivers: the experiment designs of the method on top of the C ABI.
+
+Each driver builds cells, runs them through the native sweep driver
+(``sweep_run``: back-to-back launches, per-cell events and clock windows,
+one synchronisation) or the graph-batched path (``sweep_batched``), and
+summarises the launches with :mod:`stats`.
+
+plain_k_sweep      Section 3 / Section 4.2: fixed-work K sweep at several
+                   occupancies, ascending and reversed order.
+allocation_sweep   Section 3 "Allocation-size sweep" / Section 4.2: the
+                   same fixed work over allocations of different size.
+path_comparison    Section 4.3: LDS-direct loads against the matched
+                   register path at equal in-flight depth.
+two_stream         Section 4.4: two co-resident streams in one workgroup,
+                   displacement against each stream running solo.
+batched_autotuned  64 uneven sweep points with per-size-class tuned
+                   (vector width, K, waves, cache policy), captured in one
+                   hipGraph, against the same points launched one by one
+                   at the untuned default.
+precision_sum      streaming FP32 / BF16 / FP8 sum with compensated FP32
+                   accumulation and an FP64 final combine.
+"""
+import json
+import math
+import os
+
+import torch
+
+from . import ilpsweep as isw
+from . import stats
+
+SEED_BASE = 0x1D5EED00
+GIB = 1 << 30
+MIB = 1 << 20
+
+
+def device_buffer(nbytes, seed):
+    """A seeded device buffer (SplitMix64 words) of ``nbytes`` bytes."""
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    isw.sweep_fill_u32(buf, int(nbytes), seed)
+    torch.cuda.synchronize()
+    return buf
+
+
+def _feasible(cell):
+    """True if the cell's kernel can reach the cell's residency."""
+    try:
+        isw.sweep_run([cell])
+        return True
+    except isw.SweepError as e:
+        if e.code == isw.EOCCUPANCY:
+            return False
+        raise
+
+
+def _median(v):
+    return stats.median(v) if v else None
+
+
+# ------------------------------------------------------------- K sweep (C2)
+def plain_k_cells(buf, nbytes, L, policy, waves_list, Ks, orders=("asc", "rev"),
+                  vec_width=16):
+    """Cells of a K sweep, grouped by occupancy, each order in turn."""
+    cells, meta = [], []
+    for w in waves_list:
+        for order in orders:
+            ks = list(Ks) if order == "asc" else list(reversed(list(Ks)))
+            for K in ks:
+                c = isw.make_cell(buf, nbytes, K, vec_width, w, L,
+                                  cache_policy=policy)
+                cells.append(c)
+                meta.append({"waves_per_cu": w, "order": order, "K": K})
+    return cells, meta
+
+
+def drop_infeasible(cells, meta):
+    seen = {}
+    keep_c, keep_m, dropped = [], [], []
+    for c, m in zip(cells, meta):
+        key = (c.kind, c.K, c.vec_width, c.waves_per_cu, c.cache_policy)
+        if key not in seen:
+            seen[key] = _feasible(c)
+        if seen[key]:
+            keep_c.append(c)
+            keep_m.append(m)
+        else:
+            dropped.append(dict(m))
+    return keep_c, keep_m, dropped
+
+
+def summarize_k_sweep(meta, runs, vec_width=16):
+    """Summary of repeated K-sweep passes (``runs``: list of result lists)."""
+    by = {}
+    checks = {}
+    for results in runs:
+        for m, r in zip(meta, results):
+            key = (m["waves_per_cu"], m["order"])
+            by.setdefault(key, {}).setdefault(m["K"], []).append(r["gbps"])
+            checks.setdefault(r["issued_loads"], set()).add((r["sum32"], r["xor32"]))
+    out = {"curves": {}, "checksums_consistent": all(len(v) == 1 for v in checks.values())}
+    waves = sorted({k[0] for k in by})
+    for w in waves:
+        samples = {}
+        per_order = {}
+        for order in ("asc", "rev"):
+            s = by.get((w, order))
+            if not s:
+                continue
+            per_order[order] = stats.summarize_curve(s)
+            for K, v in s.items():
+                samples.setdefault(K, []).extend(v)
+        summ = stats.summarize_curve(samples)
+        summ["by_order"] = {o: {"decline_2_8": v.get("decline_2_8"),
+                                "peak_K": v["peak_K"]}
+                            for o, v in per_order.items()}
+        n_waves = None
+        for m, r in zip(meta, runs[0]):
+            if m["waves_per_cu"] == w:
+                n_waves = r["waves"]
+                break
+        summ["in_flight_bytes"] = {
+            K: stats.in_flight_bytes(n_waves, K, vec_width) for K in summ["median_gbps"]}
+        summ["implied_latency_ns"] = {
+            K: stats.implied_latency_ns(summ["in_flight_bytes"][K], g)
+            for K, g in summ["median_gbps"].items() if g > 0}
+        out["curves"][w] = summ
+    issued = [r["issued_loads"] for r in runs[0]]
+    out["kset_mismatch"] = stats.kset_mismatch(issued) if issued else None
+    out["residency_flags"] = sum(
+        stats.residency_flag(r["gbps"], r["issued_bytes"]) for res in runs for r in res)
+    best_w = max(out["curves"], key=lambda w: max(out["curves"][w]["median_gbps"].values()))
+    out["best_waves_per_cu"] = best_w
+    out["peak_gbps"] = max(out["curves"][best_w]["median_gbps"].values())
+    return out
+
+
+def plain_k_sweep(buf, nbytes, L, policy, waves_list, Ks, passes=3, warmup=1):
+    cells, meta = plain_k_cells(buf, nbytes, L, policy, waves_list, Ks)
+    cells, meta, dropped = drop_infeasible(cells, meta)
+    for _ in range(warmup):
+        isw.sweep_run(cells)
+    runs = [isw.sweep_run(cells) for _ in range(passes)]
+    out = summarize_k_sweep(meta, runs)
+    out["infeasible"] = dropped
+    return out
+
+
+# -------------------------------------------------- allocation sweep (C3)
+def allocation_sweep(sizes, Ks=(1, 2, 4, 8), waves_list=(16,), L=1 << 30,
+                     policy=isw.CACHE_BYPASS_L1, n=3, seed=SEED_BASE + 2):
+    """Fixed-work K sweep over prefixes of one buffer of the largest size."""
+    top = max(sizes)
+    buf = device_buffer(top, seed)
+    out = {}
+    for size in sizes:
+        cells, meta = plain_k_cells(buf, size, L, policy, waves_list, Ks)
+        cells, meta, dropped = drop_infeasible(cells, meta)
+        isw.sweep_run(cells)                       # warm-up pass, excluded
+        runs = [isw.sweep_run(cells) for _ in range(n)]
+        summ = summarize_k_sweep(meta, runs)
+        out[size] = {
+            "issued_bytes": runs[0][0]["issued_bytes"],
+            "volume_to_allocation": runs[0][0]["issued_bytes"] / size,
+            "curves": {w: {"median_gbps": c["median_gbps"],
+                           "decline_2_8": c.get("decline_2_8"),
+                           "by_order": c["by_order"]}
+                       for w, c in summ["curves"].items()},
+            "checksums_consistent": summ["checksums_consistent"],
+        }
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+# ------------------------------------------------- path comparison (C4)
+def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8),
+                    policy=isw.CACHE_DEFAULT, n=3):
+    cells, meta = [], []
+    for W in waves_list:
+        for order in ("asc", "rev"):
+            ds = list(depths) if order == "asc" else list(reversed(list(depths)))
+            for D in ds:
+                for kind in (isw.KIND_LDS_ASYNC, isw.KIND_LDS_MATCHED):
+                    cells.append(isw.make_cell(buf, nbytes, D, 16, W, L, kind=kind,
+                                               cache_policy=policy))
+                    meta.append((W, D, kind))
+    isw.sweep_run(cells)
+    samples = {}
+    sums = {}
+    for _ in range(n):
+        for m, r in zip(meta, isw.sweep_run(cells)):
+            samples.setdefault(m, []).append(r["gbps"])
+            sums.setdefault(m[:2], set()).add((r["sum32"], r["xor32"]))
+    # both kinds read the same map at each (waves, depth): equal sinks
+    out = {"checksums_equal_across_paths": all(len(v) == 1 for v in sums.values())}
+    for W in waves_list:
+        row = {}
+        for D in depths:
+            a = _median(samples[(W, D, isw.KIND_LDS_ASYNC)])
+            b = _median(samples[(W, D, isw.KIND_LDS_MATCHED)])
+            row[D] = {"async_gbps": a, "matched_gbps": b, "ratio": a / b}
+        out[W] = row
+    return out
+
+
+def two_stream(buf, nbytes, L, depths=(4, 8), waves=(4, 4), n=3,
+               policy=isw.CACHE_DEFAULT):
+    wa, wb = waves
+    opts = isw.make_opts(cache_policy=policy)
+    out = {}
+    for D in depths:
+        res = {"co": [], "solo_a": [], "solo_b": []}
+        isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+        for _ in range(n):
+            a, b = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+            res["co"].append((a["gbps"], b["gbps"]))
+            a, _ = isw.sweep_two_stream(buf, nbytes, D, wa, 0, L, opts)
+            res["solo_a"].append(a["gbps"])
+            _, b = isw.sweep_two_stream(buf, nbytes, D, 0, wb, L, opts)
+            res["solo_b"].append(b["gbps"])
+        co_a = _median([x[0] for x in res["co"]])
+        co_b = _median([x[1] for x in res["co"]])
+        sa, sb = _median(res["solo_a"]), _median(res["solo_b"])
+        out[D] = {"co_a_gbps": co_a, "co_b_gbps": co_b, "solo_a_gbps": sa,
+                  "solo_b_gbps": sb, "displacement_a": 1 - co_a / sa,
+                  "displacement_b": 1 - co_b / sb, "waves": [wa, wb]}
+    return out
+
+
+# ------------------------------------------ autotuned batched sweep (C5a)
+def point_sizes(n=64, lo_log2=20, hi_log2=31, align=64 * 1024):
+    """n log-spaced sizes from 2**lo_log2 to 2**hi_log2 bytes, aligned."""
+    out = []
+    for i in range(n):
+        s = 2.0 ** (lo_log2 + (hi_log2 - lo_log2) * i / (n - 1))
+        out.append(max(align, int(round(s / align)) * align))
+    return out
+
+
+SIZE_CLASS_EDGES = [4 * MIB, 16 * MIB, 64 * MIB, 256 * MIB, GIB]
+
+
+def size_class(nbytes):
+    for i, e in enumerate(SIZE_CLASS_EDGES):
+        if nbytes < e:
+            return i
+    return len(SIZE_CLASS_EDGES)
+
+
+DEFAULT_SPACE = {"vec_widths": [16, 8], "Ks": [1, 2, 4, 8, 16],
+                 "waves_per_cu": [4, 8, 16, 32],
+                 "policies": [isw.CACHE_DEFAULT, isw.CACHE_NT,
+                              isw.CACHE_BYPASS_L1, isw.CACHE_BYPASS_L1_NT]}
+
+
+def autotune(buf_for_size, sizes, space=None, reps=3, cache_path=None,
+             device_key=None):
+    """Best (V, K, waves, policy) per size class; cached as JSON if asked."""
+    space = space or DEFAULT_SPACE
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f).get(device_key or "default", {})
+    classes = {}
+    for s in sizes:
+        classes.setdefault(size_class(s), []).append(s)
+    table = {}
+    for cls, members in sorted(classes.items()):
+        if str(cls) in cache:
+            table[cls] = cache[str(cls)]
+            continue
+        rep = members[len(members) // 2]
+        buf = buf_for_size(rep)
+        best, best_g = None, -1.0
+        for pol in space["policies"]:
+            cfg, g = isw.sweep_autotune(buf, rep, space["vec_widths"], space["Ks"],
+                                        space["waves_per_cu"], pol, reps)
+            if g > best_g:
+                best, best_g = cfg, g
+        best["tuned_gbps"] = best_g
+        best["tuned_at_bytes"] = rep
+        table[cls] = best
+    if cache_path:
+        allc = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                allc = json.load(f)
+        allc[device_key or "default"] = {str(k): v for k, v in table.items()}
+        with open(cache_path, "w") as f:
+            json.dump(allc, f, indent=1)
+    return table
+
+
+def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1),
+                      seed=SEED_BASE + 4, cache_path=None, space=None):
+    sizes = point_sizes(n_points)
+    offs, off = [], 0
+    for s in sizes:
+        offs.append(off)
+        off += s
+    big = device_buffer(off, seed)
+    base = big.data_ptr()
+
+    def buf_for(size):
+        # tune on the largest point's region of a class-sized prefix
+        return base
+
+    table = autotune(buf_for, sizes, space=space, cache_path=cache_path)
+    tuned, plain = [], []
+    for s, o in zip(sizes, offs):
+        t = table[size_class(s)]
+        V = t["vec_width"]
+        tuned.append(isw.make_cell(base + o, s, t["K"], V, t["waves_per_cu"], s // V,
+                                   cache_policy=t["cache_policy"]))
+        V0, K0, w0, p0 = default
+        plain.append(isw.make_cell(base + o, s, K0, V0, w0, s // V0, cache_policy=p0))
+    isw.sweep_batched(tuned)
+    isw.sweep_run(plain)
+    g_runs, g_ms, p_runs = [], [], []
+    for _ in range(n):
+        r, ms = isw.sweep_batched(tuned)
+        g_runs.append(r)
+        g_ms.append(ms)
+        p_runs.append(isw.sweep_run(plain))
+    sums_ok = all((a["sum32"], a["xor32"]) == (b["sum32"], b["xor32"])
+                  for a, b in zip(g_runs[0], p_runs[0]))
+    pts = []
+    for i, s in enumerate(sizes):
+        gb = _median([r[i]["gbps"] for r in g_runs])
+        pb = _median([r[i]["gbps"] for r in p_runs])
+        pts.append({"bytes": s, "batched_gbps": gb, "plain_gbps": pb,
+                    "hbm_targeted": s > stats.INFINITY_CACHE_BYTES})
+    hbm = [p for p in pts if p["hbm_targeted"]]
+    plain_ms = _median([sum(r["event_ms"] for r in run) for run in p_runs])
+    out = {
+        "sizes": len(sizes),
+        "total_bytes": off,
+        "tuned": {str(k): v for k, v in table.items()},
+        "points": pts,
+        "graph_ms": _median(g_ms),
+        "plain_kernel_ms_sum": plain_ms,
+        "batched_peak_gbps": max(p["batched_gbps"] for p in hbm),
+        "plain_peak_gbps": max(p["plain_gbps"] for p in hbm),
+        "batched_aggregate_gbps": off / (_median(g_ms) * 1e6),
+        "checksums_equal": sums_ok,
+    }
+    out["batched_peak_frac"] = out["batched_peak_gbps"] / stats.HBM_PEAK_GBPS
+    out["plain_peak_frac"] = out["plain_peak_gbps"] / stats.HBM_PEAK_GBPS
+    del big
+    torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------- precision reduction (C5b)
+def precision_sum(payload_bytes=4 * GIB, n=10, waves_per_cu=32, seed=SEED_BASE + 5):
+    import synth
+    out = {}
+    for kind, dt in (("f32", isw.F32), ("bf16", isw.BF16), ("fp8_e4m3", isw.FP8_E4M3)):
+        eb = synth.ELEM_BYTES[kind]
+        n_el = payload_bytes // eb
+        p = synth.normal_payload(kind, n_el, seed, device="cuda")
+        torch.cuda.synchronize()
+        isw.sweep_reduce_fp(p, n_el, dt, waves_per_cu)
+        gs, sums = [], []
+        for _ in range(n):
+            s, r = isw.sweep_reduce_fp(p, n_el, dt, waves_per_cu)
+            gs.append(r["gbps"])
+            sums.append(s)
+        out[kind] = {"elements": n_el, "sum": sums[0],
+                     "deterministic": len(set(sums)) == 1,
+                     "median_gbps": _median(gs),
+                     "frac_of_hbm_peak": _median(gs) / stats.HBM_PEAK_GBPS}
+        del p
+        torch.cuda.empty_cache()
+    return out
+
+
+# ------------------------------------------------------ counter pass (C3)
+def allocation_counter_pass(sizes, Ks=(2, 8), waves_per_cu=16, L=1 << 30,
+                            policy=isw.CACHE_BYPASS_L1, reps=3,
+                            seed=SEED_BASE + 2, manifest=None):
+    """Cells of the allocation sweep, one launch per call, for a separate
+    rocprofv3 counter run.  The first launch of every cell is its warm-up.
+    Returns (and optionally writes) the manifest of plain-load launches in
+    launch order, so the counter rows can be attributed to cells."""
+    buf = device_buffer(max(sizes), seed)
+    order = []
+    for size in sizes:
+        for direction in ("asc", "rev"):
+            ks = list(Ks) if direction == "asc" else list(reversed(list(Ks)))
+            for K in ks:
+                c = isw.make_cell(buf, size, K, 16, waves_per_cu, L, cache_policy=policy)
+                for rep in range(reps):
+                    r = isw.sweep_run([c])[0]
+                    order.append({"bytes": size, "K": K, "order": direction,
+                                  "rep": rep, "warmup": rep == 0,
+                                  "issued_bytes": r["issued_bytes"],
+                                  "gbps": r["gbps"]})
+    del buf
+    torch.cuda.empty_cache()
+    if manifest:
+        with open(manifest, "w") as f:
+            json.dump(order, f)
+    return order

@@ -1,0 +1,236 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+bench times: sampled per-wave checksums recomputed one by one by the oracle
+from the generator seed, global checksums through closed forms, and the
+invariants the method fixes (matched work across K, order independence)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from gpu_util import decode_recs, recs
+from oracle import checksums, fpsum, plan as oplan, splitmix
+from paper_2608_15764_amd import ilpsweep as isw
+from paper_2608_15764_amd import sweeps
+import synth
+
+GIB = 1 << 30
+
+
+def _sample(n, k=5, seed=0):
+    rng = np.random.default_rng(seed)
+    pick = {0, 1, n // 2, n - 1}
+    pick.update(int(v) for v in rng.integers(0, n, k))
+    return sorted(pick)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    nbytes = GIB
+    seed = sweeps.SEED_BASE + 1
+    buf = sweeps.device_buffer(nbytes, seed)
+    whole = checksums.whole_buffer(splitmix.buffer_words(seed, nbytes))
+    yield buf, nbytes, seed, whole
+    del buf
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("policy", [isw.CACHE_BYPASS_L1, isw.CACHE_BYPASS_L1_NT])
+@pytest.mark.parametrize("w", [4, 16, 32])
+def test_k_sweep_full_size(c2, w, policy):
+    buf, nbytes, seed, whole = c2
+    L = 1 << 26
+    issued = []
+    for K in range(1, 17):
+        n_waves = 256 * w
+        ro = recs(n_waves)
+        try:
+            r = isw.sweep_plain(buf, nbytes, K, 16, w, L,
+                                isw.make_opts(cache_policy=policy, wave_out=ro))
+        except isw.SweepError as e:
+            assert e.code == isw.EOCCUPANCY
+            continue
+        p = oplan.wave_group(L, K, r["waves"])
+        assert r["issued_loads"] == p["issued"]
+        issued.append(r["issued_loads"])
+        rr = decode_recs(ro)[: r["waves"]]
+        for wave in _sample(r["waves"], seed=K * 100 + w):
+            want = checksums.wave_from_seed(seed, 16, K, p["Q"], r["waves"], wave,
+                                            buffer_bytes=nbytes)
+            assert (rr["sum32"][wave], rr["xor32"][wave]) == want, (K, wave)
+        if K & (K - 1) == 0:        # one full pass: the whole buffer
+            assert (r["sum32"], r["xor32"]) == whole
+        assert r["gbps"] > 0
+    # matched issued logical loads across K (Section 4.2: <= 0.0246 %)
+    assert oplan.kset_mismatch(issued) <= 0.0246 / 100
+
+
+def test_orders_give_identical_results(c2):
+    buf, nbytes, _seed, _whole = c2
+    L = 1 << 26
+    cells, meta = sweeps.plain_k_cells(buf, nbytes, L, isw.CACHE_BYPASS_L1, [16],
+                                       range(1, 17))
+    res = isw.sweep_run(cells)
+    by = {}
+    for m, r in zip(meta, res):
+        by.setdefault(m["K"], set()).add((r["issued_loads"], r["sum32"], r["xor32"]))
+    assert all(len(v) == 1 for v in by.values())
+
+
+def test_residency_is_pinned(c2):
+    """Every CU hosts exactly the requested workgroups (HW_ID / XCC_ID)."""
+    buf, nbytes, _seed, _whole = c2
+    info = isw.sweep_device_info()
+    for w in (4, 8, 16, 32):
+        n_waves = info["num_cus"] * w
+        ro = recs(n_waves)
+        isw.sweep_plain(buf, nbytes, 2, 16, w, 1 << 26, isw.make_opts(wave_out=ro))
+        rr = decode_recs(ro)
+        hw = rr["hw_id"].astype(np.int64)
+        cu = (rr["xcc_id"].astype(np.int64) & 0xF) << 16 | ((hw >> 8) & 0xFF)
+        wg = np.arange(n_waves) // 4
+        per_cu = {}
+        for c, g in zip(cu, wg):
+            per_cu.setdefault(int(c), set()).add(int(g))
+        counts = sorted(len(v) for v in per_cu.values())
+        print(f"w={w}: {len(per_cu)} CUs, workgroups per CU {counts[0]}..{counts[-1]}")
+        assert len(per_cu) == info["num_cus"]
+        assert counts[0] == counts[-1] == w // 4
+
+
+@pytest.mark.parametrize("size", [512 << 20, 20 * GIB])
+def test_allocation_sweep_full_size(size):
+    seed = sweeps.SEED_BASE + 2
+    buf = sweeps.device_buffer(size, seed)
+    L = 1 << 30
+    try:
+        for K in (1, 2, 4, 8):
+            w = 16
+            ro = recs(256 * w)
+            r = isw.sweep_plain(buf, size, K, 16, w, L,
+                                isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1, wave_out=ro))
+            p = oplan.wave_group(L, K, r["waves"])
+            assert r["issued_loads"] == p["issued"] == L
+            rr = decode_recs(ro)
+            for wave in _sample(r["waves"], k=2, seed=K):
+                want = checksums.wave_from_seed(seed, 16, K, p["Q"], r["waves"], wave,
+                                                buffer_bytes=size)
+                assert (rr["sum32"][wave], rr["xor32"][wave]) == want
+            if size == 512 << 20:
+                # 16 GiB issued over 512 MiB: exactly 32 passes
+                S, _X = checksums.whole_buffer(splitmix.buffer_words(seed, size))
+                assert (r["sum32"], r["xor32"]) == ((32 * S) & 0xFFFFFFFF, 0)
+    finally:
+        del buf
+        torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    nbytes = 2 * GIB
+    seed = sweeps.SEED_BASE + 3
+    buf = sweeps.device_buffer(nbytes, seed)
+    words = splitmix.buffer_words(seed, nbytes)
+    yield buf, nbytes, seed, words
+    del buf
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", [isw.KIND_LDS_ASYNC, isw.KIND_LDS_MATCHED])
+@pytest.mark.parametrize("D,W", [(1, 1), (4, 8), (16, 8), (16, 1)])
+def test_lds_paths_full_size(c4, kind, D, W):
+    buf, nbytes, seed, words = c4
+    L = nbytes // 16
+    ro = recs(256 * W)
+    fn = isw.sweep_lds_async if kind == isw.KIND_LDS_ASYNC else isw.sweep_lds_matched_plain
+    r = fn(buf, nbytes, D, 16, W, L, isw.make_opts(wave_out=ro))
+    p = oplan.wave_group(L, D, r["waves"])
+    assert r["issued_loads"] == p["issued"] == L
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words)
+    rr = decode_recs(ro)
+    for wave in _sample(r["waves"], k=2, seed=D):
+        want = checksums.wave_from_seed(seed, 16, D, p["Q"], r["waves"], wave,
+                                        buffer_bytes=nbytes)
+        assert (rr["sum32"][wave], rr["xor32"][wave]) == want
+
+
+@pytest.mark.parametrize("D", [4, 8])
+def test_two_stream_full_size(c4, D):
+    buf, nbytes, _seed, words = c4
+    n_vec = nbytes // 16
+    (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
+    ra, rb = isw.sweep_two_stream(buf, nbytes, D, 4, 4, n_vec)
+    assert (ra["sum32"], ra["xor32"]) == checksums.whole_buffer(words[a0 * 4:(a0 + an) * 4])
+    assert (rb["sum32"], rb["xor32"]) == checksums.whole_buffer(words[b0 * 4:(b0 + bn) * 4])
+    assert ra["issued_loads"] + rb["issued_loads"] == n_vec
+
+
+def test_batched_points_full_size():
+    sizes = sweeps.point_sizes(64)
+    assert sizes[0] == 1 << 20 and sizes[-1] == 2 * GIB
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    seed = sweeps.SEED_BASE + 4
+    big = sweeps.device_buffer(int(offs[-1]), seed)
+    base = big.data_ptr()
+    cells = [isw.make_cell(base + int(o), s, 4, 16, 16, s // 16,
+                           cache_policy=isw.CACHE_BYPASS_L1_NT)
+             for s, o in zip(sizes, offs[:-1])]
+    res, ms = isw.sweep_batched(cells)
+    run = isw.sweep_run(cells)
+    assert ms > 0
+    for i, (s, o) in enumerate(zip(sizes, offs[:-1])):
+        assert res[i]["issued_bytes"] == s
+        assert (res[i]["sum32"], res[i]["xor32"]) == (run[i]["sum32"], run[i]["xor32"])
+    for i in (0, 1, 31, 62, 63):
+        w = splitmix.words(seed, int(offs[i]) // 4, sizes[i] // 4)
+        assert (res[i]["sum32"], res[i]["xor32"]) == checksums.whole_buffer(w), i
+    del big
+    torch.cuda.empty_cache()
+
+
+def test_autotuner_picks_a_candidate():
+    nbytes = 256 << 20
+    buf = sweeps.device_buffer(nbytes, 9)
+    cfg, g = isw.sweep_autotune(buf, nbytes, [16, 8], [1, 2, 4], [8, 32],
+                                isw.CACHE_NT, 2)
+    assert cfg["vec_width"] in (16, 8) and cfg["K"] in (1, 2, 4)
+    assert cfg["waves_per_cu"] in (8, 32) and g > 0
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "fp8_e4m3"])
+def test_precision_sum_full_size(kind):
+    payload_bytes = 4 * GIB
+    eb = synth.ELEM_BYTES[kind]
+    n = payload_bytes // eb
+    p = synth.normal_payload(kind, n, sweeps.SEED_BASE + 5, device="cuda")
+    dt = {"f32": isw.F32, "bf16": isw.BF16, "fp8_e4m3": isw.FP8_E4M3}[kind]
+    s1, r = isw.sweep_reduce_fp(p, n, dt, 32)
+    s2, _ = isw.sweep_reduce_fp(p, n, dt, 32)
+    assert s1 == s2                              # deterministic
+    host = p.cpu().numpy()
+    del p
+    torch.cuda.empty_cache()
+    if kind == "fp8_e4m3":
+        exact = fpsum.exact_sum_e4m3(host)
+        # sum |x| exactly from the integer multiples of 2**-9
+        t = np.abs(np.array([fpsum.e4m3_scaled_int(c)[0] for c in range(256)],
+                            dtype=np.int64))
+        absx = float(sum(int(t[host[s:s + (1 << 24)]].sum())
+                         for s in range(0, host.size, 1 << 24))) * 2.0**-9
+    else:
+        bits = host.view(np.uint32) if kind == "f32" else host.view(np.uint16)
+        vals = bits.view(np.float32) if kind == "f32" else \
+            (bits.astype(np.uint32) << np.uint32(16)).view(np.float32)
+        exact = fpsum.exact_sum(vals)
+        absx = float(np.abs(vals, dtype=np.float64).sum())
+    err = abs(s1 - exact)
+    print(f"{kind}: gpu {s1!r} exact {exact!r} |err| {err:.3e} "
+          f"({r['gbps']:.0f} GB/s)")
+    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
+    groups = (n * eb // 16) // 256
+    g_lane = -(-groups // r["waves"])
+    terms = g_lane * (4 * per_vec if kind != "fp8_e4m3" else 1) + per_vec + 16
+    assert err <= fpsum.sum2_bound(absx, terms, 8, r["grid_wgs"])

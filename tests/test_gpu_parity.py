@@ -74,7 +74,7 @@ PLAIN_CASES = [
 ]
 
 
-@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3])
 @pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES)
 def test_plain_matches_oracle(V, K, w, grid, n_vec, L, policy):
     nbytes = n_vec * V
@@ -136,7 +136,7 @@ LDS_CASES = [
 ]
 
 
-@pytest.mark.parametrize("policy", [0, 2])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind,D,W,grid,n_vec,L", LDS_CASES)
 def test_lds_paths_match_oracle(kind, D, W, grid, n_vec, L, policy):
     nbytes = n_vec * 16

@@ -1,0 +1,68 @@
+"""Counter-audit parser on synthetic rocprofv3 CSVs (no GPU)."""
+import csv
+import os
+
+import pytest
+
+from paper_2608_15764_amd import rocprof
+
+CC_FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
+             "Thread_Id", "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size",
+             "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
+             "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp",
+             "End_Timestamp"]
+
+
+def _write_cc(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=CC_FIELDS)
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": k, "Grid_Size": 1024,
+                        "Counter_Name": c, "Counter_Value": v})
+
+
+def test_warmup_failed_and_scale(tmp_path):
+    p = tmp_path / "x_counter_collection.csv"
+    K = "void ilp::plain_kload<2, 16, 2>(ilp::PlainArgs)"
+    rows = [(K, "FETCH_SIZE", 100.0),          # warm-up: excluded by rule
+            (K, "FETCH_SIZE", 524288.0),
+            (K, "FETCH_SIZE", ""),              # failed dispatch: excluded
+            (K, "FETCH_SIZE", 524300.0),
+            ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 8.0),
+            ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0),
+            ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 524290.0)]
+    _write_cc(p, rows)
+    r = rocprof.counter_rows(str(p))
+    vals, failed = rocprof.counter_values(r, "FETCH_SIZE", "plain_kload")
+    assert vals == [524288.0, 524300.0] and failed == 1
+    sc = rocprof.calib_scale(r, "FETCH_SIZE", 1 << 30)
+    assert sc == pytest.approx((1 << 30) / (524289.0 * 1024))
+    mr = rocprof.med_range(vals)
+    assert mr["median"] == 524294.0 and mr["min"] == 524288.0 and mr["n"] == 2
+
+
+def test_summary_traffic_over_algorithmic(tmp_path):
+    K = "void ilp::plain_kload<4, 16, 3>(ilp::PlainArgs)"
+    f = tmp_path / "f_counter_collection.csv"
+    w = tmp_path / "w_counter_collection.csv"
+    _write_cc(f, [(K, "FETCH_SIZE", 1.0), (K, "FETCH_SIZE", 524288.0),
+                  ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0)])
+    _write_cc(w, [(K, "WRITE_SIZE", 1.0), (K, "WRITE_SIZE", 160.0),
+                  ("__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0)])
+    s = rocprof.summary(None, str(f), str(w), "plain_kload", 1 << 30, 1 << 30)
+    assert s["fetch_scale"] == pytest.approx(2.0)
+    assert s["write_scale"] == pytest.approx(1.0)
+    assert s["hbm_bytes_per_launch"] == pytest.approx((1 << 30) + 160 * 1024)
+    assert s["traffic_over_algorithmic"] == pytest.approx(1 + 160 * 1024 / (1 << 30))
+    txt = rocprof.format_summary(s, ["cmd"], "abc")
+    assert "source_hash: abc" in txt and "hbm_bytes_per_launch:" in txt
+
+
+def test_missing_counter_gives_no_traffic(tmp_path):
+    K = "plain_kload"
+    f = tmp_path / "f_counter_collection.csv"
+    _write_cc(f, [(K, "FETCH_SIZE", ""), (K, "FETCH_SIZE", "nan")])
+    s = rocprof.summary(None, str(f), None, "plain_kload", 1 << 30)
+    assert "hbm_bytes_per_launch" not in s
+    assert s["fetch_failed_dispatches"] == 2
