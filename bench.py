@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
-                    choices=["c3", "c4", "c5a", "c5b", "c3counters"],
+                    choices=["c3", "c4", "c5a", "c5b", "c3counters", "next"],
                     help="run only one extra configuration (no K sweep); "
                          "c3counters runs the allocation-sweep cells one launch "
                          "per call for a separate rocprofv3 counter run")
@@ -307,6 +307,18 @@ def run_extras(a, isw, sweeps, only=None):
         t = time.perf_counter()
         rows["c5b_precision"] = sweeps.precision_sum()
         rows["c5b_precision"]["wall_s"] = time.perf_counter() - t
+    if only in (None, "next"):
+        t = time.perf_counter()
+        MIB = 1 << 20
+        rows["f2_f3_order_footprint"] = sweeps.order_footprint(
+            [2 * MIB, 16 * MIB, 128 * MIB, GIB, 4 * GIB])
+        rows["f2_f3_order_footprint"]["wall_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        rows["f4_regime_map"] = sweeps.regime_map()
+        rows["f4_regime_map"]["wall_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        rows["f1_latency_ladder"] = sweeps.latency_ladder()
+        rows["f1_latency_ladder"]["wall_s"] = time.perf_counter() - t
     return rows
 
 

@@ -74,6 +74,14 @@ extern "C" {
 #define SWEEP_CACHE_BYPASS_L1_NT 3 /* buffer_load ... sc1 nt: L1 bypass plus the
                                     streaming (non-temporal) hint              */
 
+/* ------------------------------------------------------- work-group order */
+/* How wave-groups are dealt to the waves (the address ordering of Section
+ * 4.2's proposed discriminating experiment; coalescing, occupancy and bytes
+ * are the same under both).  Plain kernel only. */
+#define SWEEP_ORDER_ROUND_ROBIN 0  /* wave w: q = w, w + n_waves, ...        */
+#define SWEEP_ORDER_BLOCKED     1  /* wave w: q = w*G .. w*G+G-1,
+                                      G = ceil(Q / n_waves)                    */
+
 /* ----------------------------------------------------------------- kinds */
 #define SWEEP_KIND_PLAIN        0  /* K independent loads into registers      */
 #define SWEEP_KIND_LDS_ASYNC    1  /* loads straight into LDS, no dest VGPR   */
@@ -107,6 +115,7 @@ typedef struct {
                               than the requested workgroups                 */
   sweep_wave_rec_t* wave_out; /* device, n_waves records, or NULL           */
   uint32_t* lane_out;      /* device, 2 u32 (sum, xor) per thread, or NULL  */
+  int       order;         /* SWEEP_ORDER_* (plain kernel)                  */
 } sweep_opts_t;
 
 typedef struct {
@@ -165,7 +174,18 @@ typedef struct {
   const void* buf;           /* device                                     */
   size_t      bytes;
   uint64_t    total_logical_loads;
+  int         order;         /* SWEEP_ORDER_* (plain kind only)            */
 } sweep_cell_t;
+
+/* Result of a pointer chase. */
+typedef struct {
+  uint32_t final_index;      /* index reached after warm + timed hops       */
+  uint32_t hops;             /* timed hops                                  */
+  uint64_t wall_ticks;       /* wall-clock ticks over the timed hops        */
+  double   ns_per_hop;       /* mean latency (includes sampling overhead
+                                when n_samples > 0)                         */
+  double   shader_clock_hz;  /* shader clock measured in the same window    */
+} sweep_chase_t;
 
 /* Initialise the library on HIP device `ordinal` (makes it current) and
  * allocate its scratch.  Optional: every other call initialises lazily on
@@ -188,11 +208,12 @@ int sweep_calibrate_clock(double seconds, double* hz);
  * count the grid is sized for.  Errors: SWEEP_EINVAL (K not in 1..16,
  * vec_width not 4/8/16, waves_per_cu not a multiple of 4 in 4..32, bytes 0,
  * L too small for one wave-group in fixed-work mode, fixed_iters 0 in
- * fixed-iteration mode, unknown mode), SWEEP_EALIGN (bytes not a multiple
+ * fixed-iteration mode, unknown mode or order), SWEEP_EALIGN (bytes not a multiple
  * of 64 * vec_width, so that no 64-lane segment straddles the buffer end). */
 int sweep_plan(size_t bytes, int K, int vec_width, int waves_per_cu,
                uint64_t total_logical_loads, int mode, uint32_t fixed_iters,
-               uint32_t num_cus, uint32_t grid_wgs, sweep_plan_t* out);
+               uint32_t num_cus, uint32_t grid_wgs, int order,
+               sweep_plan_t* out);
 
 /* Seeded buffer fill: 32-bit word i of `buf` becomes the low half of
  * SplitMix64 output i for state `seed` (Steele, Lea and Flood, 2014), i.e.
@@ -314,6 +335,24 @@ int sweep_autotune(const void* buf, size_t bytes,
 int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
                     int waves_per_cu, const sweep_opts_t* opt, double* sum,
                     sweep_result_t* out);
+
+/* Unloaded load latency (Section 4.1, latency ladder): one lane of one
+ * wave follows the dependent chain idx <- chain[idx] (32-bit word indices)
+ * for `warm_hops` untimed and then `hops` timed hops, so exactly one load is
+ * in flight at a time.  The first `n_samples` timed hops are also timed one
+ * by one in shader-clock cycles and written to `samples`.
+ *   chain        device, 16-byte aligned, `bytes` < 4 GiB, multiple of 4;
+ *                every reachable word must hold an index < bytes / 4
+ *   start        first index (< bytes / 4)
+ *   cache_policy SWEEP_CACHE_* of the chasing loads (default = may hit the
+ *                vector L1, bypass_l1 = .cg analogue)
+ *   samples      device, n_samples u32, or NULL with n_samples 0
+ *   n_samples    0..4096, <= hops
+ * Synchronous on `stream`.  Errors: SWEEP_EINVAL, SWEEP_EALIGN, SWEEP_EHIP. */
+int sweep_chase(const void* chain, size_t bytes, uint32_t start,
+                uint32_t warm_hops, uint32_t hops, int cache_policy,
+                uint32_t* samples, uint32_t n_samples, void* stream,
+                sweep_chase_t* out);
 
 /* Text of an error code. */
 const char* sweep_strerror(int code);

@@ -8,8 +8,12 @@ buffer, so the two pin each other on small cases.
 """
 
 
-def simulate(words, V, K, Q, n_waves, base=0, n_vec=None):
-    """Return per-lane sinks as a dict {(wave, lane): (sum32, xor32)}."""
+def simulate(words, V, K, Q, n_waves, base=0, n_vec=None, blocked=False):
+    """Return per-lane sinks as a dict {(wave, lane): (sum32, xor32)}.
+
+    Round robin: wave w takes groups w, w + n_waves, ...; blocked: wave w
+    takes the w-th run of ceil(Q / n_waves) consecutive groups.
+    """
     wpv = V // 4
     if n_vec is None:
         n_vec = len(words) // wpv - base
@@ -17,9 +21,13 @@ def simulate(words, V, K, Q, n_waves, base=0, n_vec=None):
     for w in range(n_waves):
         for lane in range(64):
             lanes[(w, lane)] = [0, 0]
+    per = (Q + n_waves - 1) // n_waves
     for w in range(n_waves):
-        q = w
-        while q < Q:                       # this wave's iterations
+        if blocked:
+            q, step, stop = w * per, 1, min(Q, (w + 1) * per)
+        else:
+            q, step, stop = w, n_waves, Q
+        while q < stop:                    # this wave's iterations
             for j in range(K):             # K independent loads
                 for lane in range(64):
                     v = base + ((q * K + j) * 64 + lane) % n_vec
@@ -28,7 +36,7 @@ def simulate(words, V, K, Q, n_waves, base=0, n_vec=None):
                         word = int(words[v * wpv + t])
                         acc[0] = (acc[0] + word) & 0xFFFFFFFF
                         acc[1] ^= word
-            q += n_waves
+            q += step
     return {k: (v[0], v[1]) for k, v in lanes.items()}
 
 

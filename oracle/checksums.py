@@ -10,8 +10,10 @@ commutative, so the result depends only on WHICH words each lane loads.
 Address map (Section 3, "Fixed-work control": the warp access is contiguous
 and fully coalesced at every K; only the per-thread offered count changes):
 
-    work unit     wave-group q = 0 .. Q-1, dealt round-robin: wave w of
-                  n_waves handles q = w, w + n_waves, ...
+    work unit     wave-group q = 0 .. Q-1, dealt to the waves round robin
+                  (wave w of n_waves handles q = w, w + n_waves, ...) or in
+                  blocks (wave w handles a contiguous range of groups); see
+                  ``plan.groups_of_wave``
     load j of K   lane l reads vector  v = ((q*K + j)*64 + l) mod n_vec
                   of a region of n_vec vectors of V bytes, starting at
                   vector ``base`` of the buffer.
@@ -23,7 +25,7 @@ consistent modulo 2**32) and reduced to uint32 at the end.
 """
 import numpy as np
 
-from . import splitmix
+from . import plan, splitmix
 
 WAVE = 64
 MASK32 = np.uint64(0xFFFFFFFF)
@@ -50,7 +52,7 @@ def _region(words_u32, V, base, n_vec):
 
 
 def per_lane(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
-             chunk_groups=4096):
+             chunk_groups=4096, order=plan.ROUND_ROBIN):
     """Per-lane (sum32, xor32), each a uint32 array [n_waves, 64]."""
     if n_vec is None:
         n_vec = words_u32.size * 4 // V - base
@@ -64,14 +66,21 @@ def per_lane(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
         gs = w.astype(np.uint64).sum(axis=(1, 3))           # [g, 64]
         gx = np.bitwise_xor.reduce(w, axis=3)
         gx = np.bitwise_xor.reduce(gx, axis=1)              # [g, 64]
-        owner = np.arange(q0, q1) % n_waves
+        owner = _owners(q0, q1, Q, n_waves, order)
         np.add.at(s, owner, gs)
         np.bitwise_xor.at(x, owner, gx)
     return (s & MASK32).astype(np.uint32), x
 
 
+def _owners(q0, q1, Q, n_waves, order):
+    q = np.arange(q0, q1)
+    if order == plan.ROUND_ROBIN:
+        return q % n_waves
+    return q // -(-Q // n_waves)
+
+
 def per_wave(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
-             chunk_groups=4096):
+             chunk_groups=4096, order=plan.ROUND_ROBIN):
     """Per-wave (sum32, xor32), each a uint32 array [n_waves]."""
     if n_vec is None:
         n_vec = words_u32.size * 4 // V - base
@@ -84,7 +93,7 @@ def per_wave(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
         w = vec[v].reshape(q1 - q0, -1)                     # [g, K*64*V/4]
         gs = w.astype(np.uint64).sum(axis=1)
         gx = np.bitwise_xor.reduce(w, axis=1)
-        owner = np.arange(q0, q1) % n_waves
+        owner = _owners(q0, q1, Q, n_waves, order)
         np.add.at(s, owner, gs)
         np.bitwise_xor.at(x, owner, gx)
     return (s & MASK32).astype(np.uint32), x
@@ -105,7 +114,7 @@ def whole_buffer(words_u32):
 
 
 def wave_from_seed(seed, V, K, Q, n_waves, wave, base=0, n_vec=None,
-                   buffer_bytes=None):
+                   buffer_bytes=None, order=plan.ROUND_ROBIN):
     """(sum32, xor32) of one wave, generating only the words it reads.
 
     Used for sampled checks on buffers too large to hold on the host: the
@@ -118,7 +127,7 @@ def wave_from_seed(seed, V, K, Q, n_waves, wave, base=0, n_vec=None,
     wpv = V // 4
     s = 0
     x = 0
-    for q in range(wave, Q, n_waves):
+    for q in plan.groups_of_wave(wave, Q, n_waves, order):
         f0 = q * K * WAVE
         # the group's K*64 vectors are consecutive modulo n_vec
         f = np.arange(f0, f0 + K * WAVE, dtype=np.int64) % n_vec + base
@@ -131,12 +140,13 @@ def wave_from_seed(seed, V, K, Q, n_waves, wave, base=0, n_vec=None,
     return s & 0xFFFFFFFF, x
 
 
-def lane_from_seed(seed, V, K, Q, n_waves, wave, lane, n_vec):
+def lane_from_seed(seed, V, K, Q, n_waves, wave, lane, n_vec,
+                   order=plan.ROUND_ROBIN):
     """(sum32, xor32) of one lane, generating only the words it reads."""
     wpv = V // 4
     s = 0
     x = 0
-    for q in range(wave, Q, n_waves):
+    for q in plan.groups_of_wave(wave, Q, n_waves, order):
         for j in range(K):
             v = vector_index(q, j, lane, K, n_vec)
             w = splitmix.words(seed, v * wpv, wpv)

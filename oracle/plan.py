@@ -37,16 +37,37 @@ def per_thread_floor(L, threads, K):
             "issued": iters * K * threads}
 
 
-def wave_group(L, K, n_waves):
-    """Wave-group fixed-work plan.
+ROUND_ROBIN, BLOCKED = 0, 1
 
-    Wave ``w`` (0 <= w < n_waves) handles groups q = w, w + n_waves, ...
-    below Q, so its iteration count is the number of such q.
+
+def groups_of_wave(w, Q, n_waves, order=ROUND_ROBIN):
+    """The wave-groups wave ``w`` handles, in the order it handles them.
+
+    round robin: q = w, w + n_waves, ... (neighbouring waves read
+                 neighbouring groups at the same time);
+    blocked:     q = w*G .. w*G + G - 1 with G = ceil(Q / n_waves) (every
+                 wave streams its own contiguous range).
+    Either way every group below Q is handled exactly once.
     """
+    if order == ROUND_ROBIN:
+        return range(w, Q, n_waves)
+    G = -(-Q // n_waves)
+    return range(min(Q, w * G), min(Q, (w + 1) * G))
+
+
+def owner(q, Q, n_waves, order=ROUND_ROBIN):
+    """The wave that handles group ``q``."""
+    if order == ROUND_ROBIN:
+        return q % n_waves
+    return q // -(-Q // n_waves)
+
+
+def wave_group(L, K, n_waves, order=ROUND_ROBIN):
+    """Wave-group fixed-work plan: Q = floor(L / 64K) groups over n_waves."""
     if K <= 0 or n_waves <= 0:
         raise ValueError("K and n_waves must be positive")
     Q = L // (WAVE * K)
-    iters = [len(range(w, Q, n_waves)) for w in range(n_waves)]
+    iters = [len(groups_of_wave(w, Q, n_waves, order)) for w in range(n_waves)]
     return {"Q": Q, "issued": WAVE * K * Q, "iters": iters,
             "iters_min": min(iters), "iters_max": max(iters)}
 

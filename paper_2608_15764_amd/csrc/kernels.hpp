@@ -13,9 +13,11 @@ namespace ilp {
 constexpr int kMaxK = 16;
 constexpr int kPlainWgThreads = 256;   // 4 waves, one per SIMD
 
-// Plain K-load cell.  Wave w of n_waves handles wave-groups q = w, w +
-// n_waves, ... below Q; load j of group q reads the 64 vectors starting at
-// vector (q*K + j)*64 mod n_vec.  `stride` is (n_waves*K*64) mod n_vec.
+// Plain K-load cell.  Round robin: wave w of n_waves handles wave-groups
+// q = w, w + n_waves, ... below Q; blocked: q = w*G .. w*G + G - 1.  Load j
+// of group q reads the 64 vectors starting at vector (q*K + j)*64 mod n_vec.
+// `stride` is the vector step between a wave's consecutive groups, mod
+// n_vec: n_waves*K*64 (round robin) or K*64 (blocked).
 struct PlainArgs {
   const uint8_t* buf;
   uint64_t n_vec;
@@ -23,6 +25,8 @@ struct PlainArgs {
   uint64_t stride;
   sweep_wave_rec_t* rec;
   uint32_t* lane_out;
+  uint64_t G;          // groups per wave in blocked order
+  uint32_t order;      // SWEEP_ORDER_*
 };
 
 // LDS-ring cell (async or matched), `waves` waves per workgroup.
@@ -60,6 +64,20 @@ struct ReduceArgs {
   sweep_wave_rec_t* rec;
 };
 
+// Pointer chase: buf[idx] holds the next index (32-bit words); `out`
+// receives {final index, wall t0, wall t1, shader-clock t0, shader-clock t1}.
+constexpr uint32_t kMaxChaseSamples = 4096;
+struct ChaseArgs {
+  const uint32_t* buf;
+  uint32_t n_bytes;        // buffer bytes (< 4 GiB)
+  uint32_t start;
+  uint32_t warm;           // untimed hops
+  uint32_t steps;          // timed hops
+  uint32_t n_samples;      // per-hop cycle samples (first hops), <= 4096
+  uint32_t* samples;       // device [n_samples] or null if n_samples == 0
+  uint64_t* out;           // device [5]
+};
+
 // Per-cell result reduced on the device from the wave records.
 struct CellRes {
   uint64_t sum;   // low 32 bits used
@@ -82,6 +100,10 @@ const void* two_stream_kernel(int D, int policy);
 hipError_t launch_two_stream(int D, int policy, uint32_t grid,
                              uint32_t wg_threads, size_t lds_bytes,
                              hipStream_t st, const TwoStreamArgs& a);
+
+// ---- pointer chase (kernels_chase.hip)
+const void* chase_kernel(int policy);
+hipError_t launch_chase(int policy, hipStream_t st, const ChaseArgs& a);
 
 // ---- fill, finishing, clock, reduction (kernels_misc.hip)
 hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,

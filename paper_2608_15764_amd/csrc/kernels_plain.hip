@@ -22,11 +22,18 @@ __global__ __launch_bounds__(kPlainWgThreads) void plain_kload(PlainArgs a) {
   const uint32_t n_waves = gridDim.x * (kPlainWgThreads / kWave);
 
   uint32_t s = 0, x = 0;
-  // start vector of this wave's first group, and the per-iteration step,
-  // both modulo the buffer's vector count (wave-uniform, scalar registers)
-  uint64_t p = ((uint64_t)wid * (K * kWave)) % a.n_vec;
+  // this wave's groups: [q0, q1) in steps of qs (wave-uniform scalars)
+  uint64_t q0 = wid, q1 = a.Q, qs = n_waves;
+  if (a.order == SWEEP_ORDER_BLOCKED) {
+    q0 = (uint64_t)wid * a.G;
+    q1 = q0 + a.G < a.Q ? q0 + a.G : a.Q;
+    qs = 1;
+  }
+  // start vector of the first group, advanced by `stride` per iteration,
+  // both modulo the buffer's vector count
+  uint64_t p = (q0 * (K * kWave)) % a.n_vec;
 #pragma unroll 1
-  for (uint64_t q = wid; q < a.Q; q += n_waves) {
+  for (uint64_t q = q0; q < q1; q += qs) {
     typename Vec<V>::T v[K];
     uint64_t pj = p;
 #pragma unroll

@@ -53,6 +53,10 @@ int plan_cell(const PlanIn& in, Plan* out, std::string* err) {
   if (in.mode != SWEEP_FIXED_WORK && in.mode != SWEEP_FIXED_ITERS &&
       in.mode != SWEEP_PER_THREAD_FLOOR)
     return bad(err, SWEEP_EINVAL, "unknown work mode");
+  if (in.order != SWEEP_ORDER_ROUND_ROBIN && in.order != SWEEP_ORDER_BLOCKED)
+    return bad(err, SWEEP_EINVAL, "unknown work-group order");
+  if (!plain && in.order != SWEEP_ORDER_ROUND_ROBIN)
+    return bad(err, SWEEP_EINVAL, "the LDS paths deal work-groups round robin only");
 
   Plan p;
   p.wg_waves = plain ? 4u : (uint32_t)in.waves_per_cu;
@@ -86,12 +90,21 @@ int plan_cell(const PlanIn& in, Plan* out, std::string* err) {
   if (o.Q == 0) return bad(err, SWEEP_EINVAL, "L is smaller than one wave-group per wave");
   o.issued_loads = 64ull * K * o.Q;
   o.issued_bytes = o.issued_loads * (uint64_t)in.V;
-  o.iters_min = (uint32_t)(o.Q / nw);
-  o.iters_max = (uint32_t)((o.Q + nw - 1) / nw);
+  p.G = (o.Q + nw - 1) / nw;
+  if (in.order == SWEEP_ORDER_BLOCKED) {
+    // wave w handles min(G, max(0, Q - w G)) groups
+    const uint64_t last = (nw - 1) * p.G;
+    o.iters_min = (uint32_t)(o.Q > last ? std::min<uint64_t>(p.G, o.Q - last) : 0);
+    o.iters_max = (uint32_t)p.G;
+  } else {
+    o.iters_min = (uint32_t)(o.Q / nw);
+    o.iters_max = (uint32_t)p.G;
+  }
   o.mismatch = in.mode == SWEEP_FIXED_ITERS
                    ? 0.0
                    : (double)(in.L - o.issued_loads) / (double)in.L;
-  p.stride = (nw * K * 64ull) % o.n_vec;
+  p.stride = in.order == SWEEP_ORDER_BLOCKED ? (K * 64ull) % o.n_vec
+                                             : (nw * K * 64ull) % o.n_vec;
   o.lds_pad_bytes = pin_padding(p.wgs_per_cu, p.lds_ring_bytes, in.lds_per_cu,
                                 in.lds_per_wg_max);
   *out = p;

@@ -25,11 +25,13 @@ struct PlanIn {
   uint32_t grid_wgs = 0;   // 0 = automatic
   uint32_t lds_per_cu = 0;      // 0 = unknown (no padding computed)
   uint32_t lds_per_wg_max = 0;
+  int order = SWEEP_ORDER_ROUND_ROBIN;
 };
 
 struct Plan {
   sweep_plan_t pub{};
-  uint64_t stride = 0;       // (n_waves*K*64) mod n_vec
+  uint64_t stride = 0;       // vector step between a wave's groups, mod n_vec
+  uint64_t G = 0;            // groups per wave in blocked order
   uint32_t wg_waves = 0;     // waves per workgroup
   uint32_t wgs_per_cu = 0;   // residency the grid asks for
   uint32_t lds_ring_bytes = 0;  // LDS the kernel itself uses per WG

@@ -187,6 +187,7 @@ int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   in.grid_wgs = c.grid_wgs;
   in.lds_per_cu = d.lds_per_cu;
   in.lds_per_wg_max = d.lds_per_wg_max;
+  in.order = c.order;
   Prepared p;
   p.c = c;
   std::string err;
@@ -234,7 +235,7 @@ hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
   if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
   if (p.c.kind == SWEEP_KIND_PLAIN) {
     PlainArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-                p.plan.stride, rec, lane_out};
+                p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
     e = launch_plain(p.c.K, p.c.vec_width, p.c.cache_policy, p.grid, p.lds, st, a);
   } else {
     LdsArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
@@ -308,6 +309,7 @@ sweep_cell_t cell_from(int kind, const void* buf, size_t bytes, int K, int V,
   c.buf = buf;
   c.bytes = bytes;
   c.total_logical_loads = L;
+  c.order = o ? o->order : SWEEP_ORDER_ROUND_ROBIN;
   return c;
 }
 
@@ -455,7 +457,8 @@ int sweep_calibrate_clock(double seconds, double* hz) {
 
 int sweep_plan(size_t bytes, int K, int vec_width, int waves_per_cu,
                uint64_t total_logical_loads, int mode, uint32_t fixed_iters,
-               uint32_t num_cus, uint32_t grid_wgs, sweep_plan_t* out) {
+               uint32_t num_cus, uint32_t grid_wgs, int order,
+               sweep_plan_t* out) {
   if (!out) return fail(SWEEP_EINVAL, "NULL output");
   PlanIn in;
   in.bytes = bytes;
@@ -468,6 +471,7 @@ int sweep_plan(size_t bytes, int K, int vec_width, int waves_per_cu,
   in.fixed_iters = fixed_iters;
   in.num_cus = num_cus;
   in.grid_wgs = grid_wgs;
+  in.order = order;
   Plan p;
   std::string err;
   int rc = plan_cell(in, &p, &err);
@@ -792,6 +796,46 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
     r.xr = 0;
     fill_result(*d, p, r, ms, out);
   }
+  return SWEEP_OK;
+}
+
+int sweep_chase(const void* chain, size_t bytes, uint32_t start,
+                uint32_t warm_hops, uint32_t hops, int cache_policy,
+                uint32_t* samples, uint32_t n_samples, void* stream,
+                sweep_chase_t* out) {
+  if (!out || !chain) return fail(SWEEP_EINVAL, "NULL argument");
+  if (bytes == 0 || bytes >= (1ull << 32)) return fail(SWEEP_EINVAL, "chain must be below 4 GiB");
+  if (bytes % 4 || reinterpret_cast<uintptr_t>(chain) % 16)
+    return fail(SWEEP_EALIGN, "chain must be 16-byte aligned and whole words");
+  if (start >= bytes / 4) return fail(SWEEP_EINVAL, "start index outside the chain");
+  if (cache_policy < 0 || cache_policy > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
+  if (hops == 0) return fail(SWEEP_EINVAL, "no timed hops");
+  if (n_samples > kMaxChaseSamples || n_samples > hops || (n_samples && !samples))
+    return fail(SWEEP_EINVAL, "n_samples must be <= 4096 and <= hops, with a buffer");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  size_t cap = 0;
+  uint64_t* dout = nullptr;
+  SW_TRY(ensure_dev(dout, cap, 5));
+  ChaseArgs a{static_cast<const uint32_t*>(chain), (uint32_t)bytes, start, warm_hops,
+              hops, n_samples, samples, dout};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t h[5] = {0, 0, 0, 0, 0};
+  hipError_t e = launch_chase(cache_policy, st, a);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return fail(SWEEP_EHIP, std::string("chase: ") + hipGetErrorString(e));
+  sweep_chase_t o;
+  std::memset(&o, 0, sizeof(o));
+  o.final_index = (uint32_t)h[0];
+  o.hops = hops;
+  o.wall_ticks = h[2] - h[1];
+  const double secs = (double)o.wall_ticks / d->hz();
+  o.ns_per_hop = secs * 1e9 / hops;
+  o.shader_clock_hz = secs > 0 ? (double)(h[4] - h[3]) / secs : 0.0;
+  *out = o;
   return SWEEP_OK;
 }
 

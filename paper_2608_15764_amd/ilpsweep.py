@@ -20,6 +20,7 @@ FIXED_WORK, FIXED_ITERS, PER_THREAD_FLOOR = 0, 1, 2
 CACHE_DEFAULT, CACHE_NT, CACHE_BYPASS_L1, CACHE_BYPASS_L1_NT = 0, 1, 2, 3
 POLICY_NAMES = {"default": 0, "nt": 1, "bypass_l1": 2, "bypass_l1_nt": 3}
 KIND_PLAIN, KIND_LDS_ASYNC, KIND_LDS_MATCHED = 0, 1, 2
+ORDER_ROUND_ROBIN, ORDER_BLOCKED = 0, 1
 F32, BF16, FP8_E4M3 = 0, 1, 2
 
 
@@ -33,7 +34,8 @@ class sweep_opts_t(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("cache_policy", C.c_int),
                 ("mode", C.c_int), ("fixed_iters", C.c_uint32),
                 ("grid_wgs", C.c_uint32), ("pin_occupancy", C.c_int),
-                ("wave_out", C.c_void_p), ("lane_out", C.c_void_p)]
+                ("wave_out", C.c_void_p), ("lane_out", C.c_void_p),
+                ("order", C.c_int)]
 
 
 class sweep_result_t(C.Structure):
@@ -78,12 +80,22 @@ class sweep_device_t(C.Structure):
         return d
 
 
+class sweep_chase_t(C.Structure):
+    _fields_ = [("final_index", C.c_uint32), ("hops", C.c_uint32),
+                ("wall_ticks", C.c_uint64), ("ns_per_hop", C.c_double),
+                ("shader_clock_hz", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class sweep_cell_t(C.Structure):
     _fields_ = [("kind", C.c_int), ("K", C.c_int), ("vec_width", C.c_int),
                 ("waves_per_cu", C.c_int), ("cache_policy", C.c_int),
                 ("mode", C.c_int), ("fixed_iters", C.c_uint32),
                 ("grid_wgs", C.c_uint32), ("buf", C.c_void_p),
-                ("bytes", C.c_size_t), ("total_logical_loads", C.c_uint64)]
+                ("bytes", C.c_size_t), ("total_logical_loads", C.c_uint64),
+                ("order", C.c_int)]
 
 
 # symbol -> (restype, argtypes); every function declared in the header
@@ -95,7 +107,7 @@ _SIG = {
     "sweep_calibrate_clock": (C.c_int, [C.c_double, C.POINTER(C.c_double)]),
     "sweep_plan": (C.c_int, [C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_uint64,
                              C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
-                             C.POINTER(sweep_plan_t)]),
+                             C.c_int, C.POINTER(sweep_plan_t)]),
     "sweep_fill_u32": (C.c_int, [_P, C.c_size_t, C.c_uint64, _P]),
     "sweep_plain": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
                               C.c_uint64, C.POINTER(sweep_opts_t),
@@ -125,6 +137,9 @@ _SIG = {
                                   C.POINTER(sweep_opts_t),
                                   C.POINTER(C.c_double),
                                   C.POINTER(sweep_result_t)]),
+    "sweep_chase": (C.c_int, [_P, C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint32,
+                              C.c_int, _P, C.c_uint32, _P,
+                              C.POINTER(sweep_chase_t)]),
     "sweep_strerror": (C.c_char_p, [C.c_int]),
     "sweep_last_error": (C.c_char_p, []),
     "sweep_version": (C.c_char_p, []),
@@ -176,7 +191,7 @@ def _stream(s):
 
 def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
               fixed_iters=0, grid_wgs=0, pin_occupancy=True, wave_out=None,
-              lane_out=None):
+              lane_out=None, order=ORDER_ROUND_ROBIN):
     o = sweep_opts_t()
     o.stream = _stream(stream)
     o.cache_policy = cache_policy
@@ -186,6 +201,7 @@ def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
     o.pin_occupancy = 1 if pin_occupancy else 0
     o.wave_out = _ptr(wave_out)
     o.lane_out = _ptr(lane_out)
+    o.order = order
     return o
 
 
@@ -211,11 +227,12 @@ def sweep_calibrate_clock(seconds=0.2):
 
 
 def sweep_plan(bytes_, K, vec_width, waves_per_cu, total_logical_loads,
-               mode=FIXED_WORK, fixed_iters=0, num_cus=256, grid_wgs=0):
+               mode=FIXED_WORK, fixed_iters=0, num_cus=256, grid_wgs=0,
+               order=ORDER_ROUND_ROBIN):
     p = sweep_plan_t()
     _check(lib.sweep_plan(bytes_, K, vec_width, waves_per_cu,
                           total_logical_loads, mode, fixed_iters, num_cus,
-                          grid_wgs, C.byref(p)), "sweep_plan")
+                          grid_wgs, order, C.byref(p)), "sweep_plan")
     return p.as_dict()
 
 
@@ -263,7 +280,7 @@ def sweep_two_stream(buf, bytes_, depth, waves_plain, waves_async,
 
 def make_cell(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
               kind=KIND_PLAIN, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
-              fixed_iters=0, grid_wgs=0):
+              fixed_iters=0, grid_wgs=0, order=ORDER_ROUND_ROBIN):
     c = sweep_cell_t()
     c.kind = kind
     c.K = K
@@ -276,6 +293,7 @@ def make_cell(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
     c.buf = _ptr(buf)
     c.bytes = bytes_
     c.total_logical_loads = total_logical_loads
+    c.order = order
     return c
 
 
@@ -337,6 +355,15 @@ def sweep_reduce_fp(payload, n_elems, dtype, waves_per_cu=32, opts=None):
                                C.byref(o), C.byref(s), C.byref(r)),
            "sweep_reduce_fp")
     return s.value, r.as_dict()
+
+
+def sweep_chase(chain, bytes_, start, warm_hops, hops, cache_policy=CACHE_DEFAULT,
+                samples=None, n_samples=0, stream=None):
+    o = sweep_chase_t()
+    _check(lib.sweep_chase(_ptr(chain), bytes_, start, warm_hops, hops,
+                           cache_policy, _ptr(samples), n_samples,
+                           _stream(stream), C.byref(o)), "sweep_chase")
+    return o.as_dict()
 
 
 def sweep_strerror(code):

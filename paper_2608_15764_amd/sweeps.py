@@ -402,3 +402,143 @@ def allocation_counter_pass(sizes, Ks=(2, 8), waves_per_cu=16, L=1 << 30,
         with open(manifest, "w") as f:
             json.dump(order, f)
     return order
+
+
+# --------------------------- order and footprint experiment (next rows f2, f3)
+def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
+                    policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 6):
+    """The fixed-work K sweep under both work-group orders, at allocations
+    below, around and above the caches (4 MiB L2 per XCD, 256 MiB last-level
+    cache).  Coalescing, occupancy and logical bytes are the same in every
+    cell; only the address ordering (round robin vs blocked) and the
+    footprint change."""
+    buf = device_buffer(max(sizes), seed)
+    out = {}
+    for size in sizes:
+        row = {}
+        for order, oname in ((isw.ORDER_ROUND_ROBIN, "round_robin"),
+                             (isw.ORDER_BLOCKED, "blocked")):
+            cells, meta = [], []
+            for direction in ("asc", "rev"):
+                ks = list(Ks) if direction == "asc" else list(reversed(list(Ks)))
+                for K in ks:
+                    cells.append(isw.make_cell(buf, size, K, 16, waves_per_cu, L,
+                                               cache_policy=policy, order=order))
+                    meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K})
+            arr = isw.cell_array(cells)
+            isw.sweep_run(arr, raw=True)
+            runs = [isw.sweep_run(arr) for _ in range(n)]
+            summ = summarize_k_sweep(meta, runs)
+            c = summ["curves"][waves_per_cu]
+            row[oname] = {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                          "decline_2_8": c.get("decline_2_8"),
+                          "by_order": c["by_order"],
+                          "residency_flags": summ["residency_flags"],
+                          "checksums_consistent": summ["checksums_consistent"]}
+        out[size] = row
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------- regime map (next row f4)
+def regime_map(waves_list=(4, 8, 12, 16, 20, 24, 28, 32), widths=(4, 8, 16),
+               Ks=range(1, 17), half_grid=True, nbytes=GIB,
+               policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 7):
+    """Response curves over occupancy x vector width (x full / half-CU
+    grids), each classified saturating / rising-censored / peak-decline by
+    the 95 % plateau rule with a three-cell tail."""
+    buf = device_buffer(nbytes, seed)
+    info = isw.sweep_device_info()
+    grids = [0] + ([info["num_cus"] // 2] if half_grid else [])
+    curves = {}
+    counts = {"saturating": 0, "rising-censored": 0, "peak-decline": 0, "infeasible": 0}
+    for g in grids:
+        for V in widths:
+            for w in waves_list:
+                L = nbytes // V if g == 0 else nbytes // (2 * V)
+                cells = []
+                keep = []
+                for K in Ks:
+                    c = isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
+                                      grid_wgs=(g * w // 4) if g else 0)
+                    if _feasible(c):
+                        cells.append(c)
+                        keep.append(K)
+                if len(keep) < 3:
+                    counts["infeasible"] += 1
+                    continue
+                arr = isw.cell_array(cells)
+                samples = {K: [] for K in keep}
+                for _ in range(n):
+                    for K, r in zip(keep, isw.sweep_run(arr)):
+                        samples[K].append(r["gbps"])
+                med = stats.per_k_medians(samples)
+                reg = stats.classify(med)
+                counts[reg] += 1
+                key = f"{'half' if g else 'full'}_V{V}_w{w}"
+                curves[key] = {"regime": reg, "peak_K": stats.peak_k(med),
+                               "peak_gbps": round(max(med.values()), 1),
+                               "decline_2_8": (stats.decline(med[2], med[8])
+                                               if 2 in med and 8 in med else None)}
+    del buf
+    torch.cuda.empty_cache()
+    return {"counts": counts, "curves": curves}
+
+
+# ------------------------------------------- latency ladder (next row f1)
+def latency_ladder(footprints=None, stride=128, hops=8192, n_samples=4096,
+                   policies=(isw.CACHE_DEFAULT, isw.CACHE_BYPASS_L1), seed=SEED_BASE + 8,
+                   evict_bytes=2 * GIB):
+    """Unloaded dependent-load latency against footprint (Section 4.1):
+    mean ns per hop over an unsampled run, and p5/p50/p95/p99 of the
+    per-hop shader-clock samples of a second run.
+
+    Footprints that fit the last-level cache are warmed by walking the chain
+    first.  Larger ones are measured cold: before every run a 2 GiB stream
+    evicts the caches, and every run continues the chain where the previous
+    one stopped, so no timed hop revisits a node an earlier run touched."""
+    import synth
+    if footprints is None:
+        footprints = [8 << 10 << i for i in range(19)]          # 8 KiB .. 2 GiB
+    names = {0: "default", 1: "nt", 2: "bypass_l1", 3: "bypass_l1_nt"}
+    evict_buf = device_buffer(evict_bytes, seed + 1)
+
+    def evict():
+        isw.sweep_plain(evict_buf, evict_bytes, 4, 16, 32, evict_bytes // 16)
+
+    out = {}
+    for fp in footprints:
+        chain, start = synth.chase_chain(fp, stride, seed + fp.bit_length(), device="cuda")
+        nodes = fp // stride
+        cold = fp > stats.INFINITY_CACHE_BYTES
+        idx = start
+        row = {}
+        samples = torch.zeros(n_samples, dtype=torch.int32, device="cuda")
+        for pol in policies:
+            res = []
+            for ns_ in (0, n_samples):
+                if cold:
+                    evict()
+                    warm = 0
+                else:
+                    warm = min(nodes, 1 << 15)
+                r = isw.sweep_chase(chain, fp, idx, warm, hops, pol,
+                                    samples if ns_ else None, ns_)
+                res.append(r)
+                if cold:
+                    idx = r["final_index"]
+            mean, dist = res
+            cyc = samples.cpu().numpy().astype("float64")
+            v = sorted(cyc / dist["shader_clock_hz"] * 1e9)
+            q = lambda p: float(v[min(len(v) - 1, int(p * len(v)))])
+            row[names[pol]] = {
+                "mean_ns": round(mean["ns_per_hop"], 2),
+                "p5_ns": round(q(0.05), 1), "p50_ns": round(q(0.50), 1),
+                "p95_ns": round(q(0.95), 1), "p99_ns": round(q(0.99), 1),
+                "cold": cold, "shader_clock_hz": dist["shader_clock_hz"]}
+        out[fp] = row
+        del chain, samples
+    del evict_buf
+    torch.cuda.empty_cache()
+    return out

@@ -11,6 +11,10 @@ Recipes
 ``normal_payload``  N(0, 1) samples drawn in FP32 and stored as FP32, BF16
                   (round to nearest even) or FP8 e4m3fn (clamped to +-448,
                   then round to nearest even), as raw little-endian bytes.
+``chase_chain``   a pointer-chase chain: one node per ``stride`` bytes of a
+                  ``footprint``-byte buffer, linked in a seeded random order
+                  into a single cycle; each node's first 32-bit word holds
+                  the word index of the next node.
 """
 import torch
 
@@ -46,3 +50,17 @@ def normal_payload(kind, n, seed, device="cpu", chunk=1 << 26):
             x = x.clamp_(-448.0, 448.0)
         view[s:s + c] = x.to(dt)
     return out
+
+
+def chase_chain(footprint, stride, seed, device="cpu"):
+    """(uint8 tensor of ``footprint`` bytes, start word index)."""
+    if footprint % stride or stride % 4:
+        raise ValueError("footprint must be a multiple of stride, stride of 4")
+    n = footprint // stride
+    step = stride // 4
+    g = _gen(seed, device)
+    order = torch.randperm(n, generator=g, device=device, dtype=torch.int64)
+    words = torch.zeros(footprint // 4, dtype=torch.int32, device=device)
+    nxt = torch.roll(order, -1)
+    words[order * step] = (nxt * step).to(torch.int32)
+    return words.view(torch.uint8), int(order[0].item()) * step

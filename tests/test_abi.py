@@ -45,7 +45,8 @@ def test_version_and_errors(isw):
 STRUCTS = {
     "sweep_wave_rec_t": ["sum32", "xor32", "hw_id", "xcc_id", "t0", "t1"],
     "sweep_opts_t": ["stream", "cache_policy", "mode", "fixed_iters",
-                     "grid_wgs", "pin_occupancy", "wave_out", "lane_out"],
+                     "grid_wgs", "pin_occupancy", "wave_out", "lane_out",
+                     "order"],
     "sweep_result_t": ["target_loads", "issued_loads", "issued_bytes",
                        "mismatch", "sum32", "xor32", "grid_wgs", "wg_threads",
                        "waves", "iters_min", "iters_max", "max_wgs_per_cu",
@@ -58,9 +59,11 @@ STRUCTS = {
                        "lds_per_wg_max", "l2_bytes", "hbm_bytes",
                        "wall_clock_hz", "calibrated_hz", "clock_khz",
                        "mem_clock_khz", "mem_bus_bits"],
+    "sweep_chase_t": ["final_index", "hops", "wall_ticks", "ns_per_hop",
+                      "shader_clock_hz"],
     "sweep_cell_t": ["kind", "K", "vec_width", "waves_per_cu", "cache_policy",
                      "mode", "fixed_iters", "grid_wgs", "buf", "bytes",
-                     "total_logical_loads"],
+                     "total_logical_loads", "order"],
 }
 
 
@@ -117,6 +120,15 @@ def test_planner_other_modes(isw):
     assert p["iters_min"] == p["iters_max"] == o["iters"]
 
 
+@pytest.mark.parametrize("K,w,L", [(1, 4, 2**26), (3, 12, 2**26 + 999), (16, 32, 10**6),
+                                   (5, 8, 64 * 5 * 7)])
+def test_planner_blocked_order(isw, K, w, L):
+    p = isw.sweep_plan(2**30, K, 16, w, L, num_cus=256, order=isw.ORDER_BLOCKED)
+    o = oplan.wave_group(L, K, 256 * w, order=oplan.BLOCKED)
+    assert p["Q"] == o["Q"] and p["issued_loads"] == o["issued"]
+    assert (p["iters_min"], p["iters_max"]) == (o["iters_min"], o["iters_max"])
+
+
 def test_planner_explicit_grid(isw):
     p = isw.sweep_plan(64 << 20, 2, 4, 4, 2**24, num_cus=0, grid_wgs=256)
     assert p["grid_wgs"] == 256 and p["waves"] == 1024
@@ -143,4 +155,7 @@ def test_planner_rejects(isw, args, code):
 def test_planner_rejects_unknown_mode(isw):
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_plan(1 << 20, 2, 16, 8, 1000, mode=7, num_cus=256)
+    assert e.value.code == -1
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plan(1 << 20, 2, 16, 8, 1000, num_cus=256, order=2)
     assert e.value.code == -1

@@ -317,3 +317,55 @@ def test_host_validation_errors():
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_fill_u32(buf.data_ptr() + 4, 64, 1)
     assert e.value.code == isw.EALIGN
+
+
+@pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES[:6])
+def test_plain_blocked_order_matches_oracle(V, K, w, grid, n_vec, L):
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=V * 7 + K, device="cuda")
+    n_waves = grid * 4
+    lo = lanes(n_waves * 64)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=isw.CACHE_BYPASS_L1_NT,
+                         lane_out=lo, order=isw.ORDER_BLOCKED)
+    r = isw.sweep_plain(buf, nbytes, K, V, w, L, opts)
+    p = oplan.wave_group(L, K, n_waves, order=oplan.BLOCKED)
+    assert r["issued_loads"] == p["issued"]
+    assert (r["iters_min"], r["iters_max"]) == (p["iters_min"], p["iters_max"])
+    ws, wx = checksums.per_lane(host_words(buf), V, K, p["Q"], n_waves,
+                                order=oplan.BLOCKED)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+
+
+def test_lds_paths_reject_blocked_order():
+    buf = dev_bytes(1 << 20)
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_lds_async(buf, 1 << 20, 4, 16, 4, 1000,
+                            isw.make_opts(order=isw.ORDER_BLOCKED))
+    assert e.value.code == isw.EINVAL
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2, 3])
+@pytest.mark.parametrize("footprint,stride,warm,hops", [(8192, 128, 64, 200),
+                                                       (1 << 20, 128, 100, 3000),
+                                                       (4096, 4, 0, 5000)])
+def test_chase_matches_oracle(footprint, stride, warm, hops, policy):
+    from oracle import chase
+    chain, start = synth.chase_chain(footprint, stride, seed=footprint + stride,
+                                     device="cuda")
+    samples = torch.zeros(min(hops, 4096), dtype=torch.int32, device="cuda")
+    r = isw.sweep_chase(chain, footprint, start, warm, hops, policy, samples,
+                        samples.numel())
+    words = host_words(chain)
+    assert r["final_index"] == chase.follow(words, start, warm + hops)
+    assert r["ns_per_hop"] > 0 and r["shader_clock_hz"] > 1e8
+    assert (samples.cpu().numpy() > 0).all()
+
+
+def test_chase_rejects_bad_arguments():
+    chain, start = synth.chase_chain(4096, 64, seed=1, device="cuda")
+    for args in [(chain, 4096, 4096 // 4, 0, 10),      # start outside
+                 (chain, 4096, start, 0, 0)]:           # no hops
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_chase(*args)
+        assert e.value.code == isw.EINVAL

@@ -135,3 +135,33 @@ def test_two_stream_regions_partition_the_buffer():
     s = (checksums.combine(sa, xa)[0] + checksums.combine(sb, xb)[0]) & 0xFFFFFFFF
     x = checksums.combine(sa, xa)[1] ^ checksums.combine(sb, xb)[1]
     assert (s, x) == checksums.whole_buffer(w)
+
+
+@pytest.mark.parametrize("V,K,Q,nw,nbytes", CASES)
+def test_blocked_order_matches_brute_force(V, K, Q, nw, nbytes):
+    w = _buf(nbytes, seed=21)
+    lanes = brute.simulate(w, V, K, Q, nw, blocked=True)
+    s, x = checksums.per_lane(w, V, K, Q, nw, order=plan.BLOCKED)
+    for (wave, lane), (ls, lx) in lanes.items():
+        assert (s[wave, lane], x[wave, lane]) == (ls, lx)
+    ws, wx = checksums.per_wave(w, V, K, Q, nw, order=plan.BLOCKED, chunk_groups=3)
+    for wave in range(nw):
+        assert checksums.wave_from_seed(21, V, K, Q, nw, wave, buffer_bytes=nbytes,
+                                        order=plan.BLOCKED) == (ws[wave], wx[wave])
+
+
+def test_orders_partition_the_same_groups():
+    for Q, nw in [(0, 3), (1, 4), (7, 3), (12, 4), (13, 4), (100, 7)]:
+        for order in (plan.ROUND_ROBIN, plan.BLOCKED):
+            seen = sorted(q for w in range(nw) for q in plan.groups_of_wave(w, Q, nw, order))
+            assert seen == list(range(Q))
+            for w in range(nw):
+                for q in plan.groups_of_wave(w, Q, nw, order):
+                    assert plan.owner(q, Q, nw, order) == w
+    # global sinks do not depend on the order
+    V, K, nw = 16, 3, 5
+    w = _buf(16 * 64 * 16, seed=22)
+    Q = 23
+    a = checksums.combine(*checksums.per_wave(w, V, K, Q, nw))
+    b = checksums.combine(*checksums.per_wave(w, V, K, Q, nw, order=plan.BLOCKED))
+    assert a == b
