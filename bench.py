@@ -152,6 +152,15 @@ def main():
     hz = isw.sweep_calibrate_clock(0.5)
     policy = isw.POLICY_NAMES[a.policy]
     out_extra = {}
+    if a.calib_copy:
+        # plain 1 GiB device copies: the known-size reference that scales
+        # the FETCH_SIZE / WRITE_SIZE counters of a separate counter run
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if a.only == "c3counters":
         GIB = 1 << 30
@@ -192,14 +201,6 @@ def main():
     best_w = summ["best_waves_per_cu"]
     cb = summ["curves"][best_w]
     w4 = summ["curves"].get(16)
-
-    if a.calib_copy:
-        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     result = {
         "metric": "attained HBM GB/s vs offered loads/thread K; % of HBM peak; K=2->8 decline %",

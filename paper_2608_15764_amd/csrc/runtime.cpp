@@ -61,6 +61,7 @@ struct Dev {
   double* dsum = nullptr;
   double* dsum_h = nullptr;
   uint64_t* clk = nullptr;
+  uint64_t* chase_out = nullptr;  // 5 words per chase call
   uint64_t* offs = nullptr;     // per-cell record offsets (device)
   size_t offs_cap = 0;
   uint64_t* offs_h = nullptr;   // pinned staging copy
@@ -150,6 +151,8 @@ int init_device(int ordinal, Dev** out) {
   SW_TRY(ensure_dev(d->dsum, one, 1));
   SW_TRY(ensure_host(d->dsum_h, one_h, 1));
   SW_TRY(ensure_dev(d->clk, clk_cap, 1));
+  size_t chase_cap = 0;
+  SW_TRY(ensure_dev(d->chase_out, chase_cap, 5));
   SW_TRY(ensure_events(*d, 8));
   g_devs[ordinal] = d;
   *out = d;
@@ -386,6 +389,7 @@ int sweep_shutdown(void) {
     if (d->dsum) (void)hipFree(d->dsum);
     if (d->dsum_h) (void)hipHostFree(d->dsum_h);
     if (d->clk) (void)hipFree(d->clk);
+    if (d->chase_out) (void)hipFree(d->chase_out);
     if (d->offs) (void)hipFree(d->offs);
     if (d->offs_h) (void)hipHostFree(d->offs_h);
     for (auto e : d->ev) (void)hipEventDestroy(e);
@@ -815,9 +819,7 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
   std::lock_guard<std::mutex> lk(g_mu);
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
-  size_t cap = 0;
-  uint64_t* dout = nullptr;
-  SW_TRY(ensure_dev(dout, cap, 5));
+  uint64_t* dout = d->chase_out;
   ChaseArgs a{static_cast<const uint32_t*>(chain), (uint32_t)bytes, start, warm_hops,
               hops, n_samples, samples, dout};
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -825,7 +827,6 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
   hipError_t e = launch_chase(cache_policy, st, a);
   if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(dout);
   if (e != hipSuccess) return fail(SWEEP_EHIP, std::string("chase: ") + hipGetErrorString(e));
   sweep_chase_t o;
   std::memset(&o, 0, sizeof(o));
