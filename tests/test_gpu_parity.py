@@ -369,3 +369,57 @@ def test_chase_rejects_bad_arguments():
         with pytest.raises(isw.SweepError) as e:
             isw.sweep_chase(*args)
         assert e.value.code == isw.EINVAL
+
+
+@pytest.mark.parametrize("V,K,n_vec,L", [(16, 4, 64, 64 * 4 * 3),      # one segment
+                                         (4, 1, 256, 64 * 5),           # Q < waves
+                                         (16, 16, 64, 64 * 16),         # one group
+                                         (8, 3, 128, 64 * 3 * 1000)])   # deep wrap
+def test_plain_degenerate_shapes(V, K, n_vec, L):
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=n_vec + K, device="cuda")
+    info = isw.sweep_device_info()
+    n_waves = info["num_cus"] * 8            # default grid at 8 waves/CU
+    ro = recs(n_waves)
+    r = isw.sweep_plain(buf, nbytes, K, V, 8, L, isw.make_opts(wave_out=ro))
+    p = oplan.wave_group(L, K, n_waves)
+    assert r["waves"] == n_waves and r["issued_loads"] == p["issued"]
+    s, x = checksums.per_wave(host_words(buf), V, K, p["Q"], n_waves)
+    rr = decode_recs(ro)
+    assert np.array_equal(rr["sum32"], s) and np.array_equal(rr["xor32"], x)
+    idle = np.array(p["iters"]) == 0
+    assert (rr["sum32"][idle] == 0).all() and (rr["xor32"][idle] == 0).all()
+
+
+def test_window_agrees_with_events():
+    nbytes = 1 << 30
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, 5)
+    isw.sweep_calibrate_clock(0.05)
+    for w in (4, 32):
+        r = isw.sweep_run([isw.make_cell(buf, nbytes, 4, 16, w, nbytes // 16)] * 3)[-1]
+        ev_ns = r["event_ms"] * 1e6
+        assert 0.85 < r["window_ns"] / ev_ns <= 1.02, (r["window_ns"], ev_ns)
+        assert abs(r["gbps"] - r["issued_bytes"] / r["window_ns"]) < 1e-6
+
+
+def test_sweep_drivers_run_small():
+    from paper_2608_15764_amd import sweeps
+    nbytes = 8 << 20
+    buf = sweeps.device_buffer(nbytes, 11)
+    out = sweeps.plain_k_sweep(buf, nbytes, nbytes // 16, isw.CACHE_BYPASS_L1_NT,
+                               [4, 32], range(1, 5), passes=2)
+    assert out["checksums_consistent"] and set(out["curves"]) == {4, 32}
+    pc = sweeps.path_comparison(buf, nbytes, nbytes // 16, depths=(1, 4), waves_list=(1, 4), n=1)
+    assert pc["checksums_equal_across_paths"] and pc[4][4]["ratio"] > 0
+    ts = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), n=1)
+    assert 4 in ts
+    al = sweeps.allocation_sweep([1 << 20, 4 << 20], Ks=(1, 2), waves_list=(8,), L=1 << 20, n=1)
+    assert all(v["checksums_consistent"] for v in al.values())
+    of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
+    assert set(of[1 << 20]) == {"round_robin", "blocked"}
+    lad = sweeps.latency_ladder(footprints=[8 << 10, 1 << 20], hops=256, n_samples=128,
+                                evict_bytes=16 << 20)
+    assert lad[8 << 10]["default"]["mean_ns"] > 0
+    ps = sweeps.precision_sum(payload_bytes=1 << 20, n=2)
+    assert all(v["deterministic"] for v in ps.values())
