@@ -1,0 +1,47 @@
+"""The C ABI used from plain C (gcc, HIP runtime only), checked against the
+oracle."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+@pytest.mark.skipif(not _gpu(), reason="needs a GPU")
+def test_plain_c_program(tmp_path):
+    from oracle import checksums, plan as oplan, splitmix
+    lib_dir = os.path.join(ROOT, "paper_2608_15764_amd")
+    exe = str(tmp_path / "c_abi_check")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    subprocess.run(["gcc", "-O2", "-D__HIP_PLATFORM_AMD__",
+                    "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_check.c"), "-o", exe,
+                    "-L", lib_dir, "-lilpsweep", "-L", os.path.join(rocm, "lib"),
+                    "-lamdhip64", f"-Wl,-rpath,{lib_dir}",
+                    f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"], check=True)
+    nbytes, seed = 64 << 20, 7
+    out = subprocess.run([exe, str(nbytes), str(seed)], check=True, capture_output=True,
+                         text=True, timeout=120).stdout
+    res = {l.split()[0]: tuple(int(v) for v in l.split()[1:]) for l in out.strip().splitlines()}
+    words = splitmix.buffer_words(seed, nbytes)
+    whole = checksums.whole_buffer(words)
+    L = nbytes // 16
+    for name, K in (("plain", 4), ("lds_async", 8), ("batched_K2", 2)):
+        assert res[name][:2] == whole and res[name][2] == L, name
+    from paper_2608_15764_amd import ilpsweep as isw
+    n_waves = isw.sweep_device_info()["num_cus"] * 32
+    p = oplan.wave_group(L, 3, n_waves)
+    want = checksums.combine(*checksums.per_wave(words, 16, 3, p["Q"], n_waves))
+    assert res["batched_K3"] == (*want, p["issued"])
