@@ -147,7 +147,9 @@ def main():
     from paper_2608_15764_amd import ilpsweep as isw
     from paper_2608_15764_amd import stats, sweeps
 
+    from paper_2608_15764_amd import environment
     torch.cuda.set_device(0)
+    env_before = environment.amd_smi_metrics()
     info = isw.sweep_device_info()
     hz = isw.sweep_calibrate_clock(0.5)
     policy = isw.POLICY_NAMES[a.policy]
@@ -191,6 +193,7 @@ def main():
     t1 = time.perf_counter()
     runs = [isw.result_dicts(r) for r in raws]
 
+    env_after = environment.amd_smi_metrics()
     step_bytes = sum(r["issued_bytes"] for r in runs[0])
     value = a.steps * step_bytes / (t1 - t0) / 1e9
     kernel_ms = sum(r["event_ms"] for run in runs for r in run)
@@ -251,6 +254,8 @@ def main():
                      "algorithmic_bytes_per_launch": step_bytes // len(cells)},
         "device": {"arch": info["arch"], "cus": info["num_cus"],
                    "clock_hz_calibrated": hz},
+        "environment": {"static": environment.static_info(),
+                        "amd_smi_before": env_before, "amd_smi_after": env_after},
     }
     if not a.no_extras:
         # one untimed pass of the same sweep under every cache policy
@@ -297,6 +302,9 @@ def run_extras(a, isw, sweeps, only=None):
         L = nbytes // 16
         rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L)
         rows["c4_two_stream"] = sweeps.two_stream(buf, nbytes, L)
+        rows["c4_two_stream_grid"] = sweeps.two_stream(
+            buf, nbytes, L, depths=(4,),
+            pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2)
         rows["c4_wall_s"] = time.perf_counter() - t
         del buf
         torch.cuda.empty_cache()

@@ -203,27 +203,31 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
     return out
 
 
-def two_stream(buf, nbytes, L, depths=(4, 8), waves=(4, 4), n=3,
+def two_stream(buf, nbytes, L, depths=(4, 8), pairs=((4, 4),), n=3,
                policy=isw.CACHE_DEFAULT):
-    wa, wb = waves
+    """Displacement of each stream by the other (Section 4.4): for every
+    depth and (plain waves, LDS-direct waves) pair per workgroup, the
+    co-resident bandwidth of each stream against the same stream solo."""
     opts = isw.make_opts(cache_policy=policy)
     out = {}
     for D in depths:
-        res = {"co": [], "solo_a": [], "solo_b": []}
-        isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
-        for _ in range(n):
-            a, b = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
-            res["co"].append((a["gbps"], b["gbps"]))
-            a, _ = isw.sweep_two_stream(buf, nbytes, D, wa, 0, L, opts)
-            res["solo_a"].append(a["gbps"])
-            _, b = isw.sweep_two_stream(buf, nbytes, D, 0, wb, L, opts)
-            res["solo_b"].append(b["gbps"])
-        co_a = _median([x[0] for x in res["co"]])
-        co_b = _median([x[1] for x in res["co"]])
-        sa, sb = _median(res["solo_a"]), _median(res["solo_b"])
-        out[D] = {"co_a_gbps": co_a, "co_b_gbps": co_b, "solo_a_gbps": sa,
-                  "solo_b_gbps": sb, "displacement_a": 1 - co_a / sa,
-                  "displacement_b": 1 - co_b / sb, "waves": [wa, wb]}
+        for wa, wb in pairs:
+            res = {"co": [], "solo_a": [], "solo_b": []}
+            isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+            for _ in range(n):
+                a, b = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+                res["co"].append((a["gbps"], b["gbps"]))
+                a, _ = isw.sweep_two_stream(buf, nbytes, D, wa, 0, L, opts)
+                res["solo_a"].append(a["gbps"])
+                _, b = isw.sweep_two_stream(buf, nbytes, D, 0, wb, L, opts)
+                res["solo_b"].append(b["gbps"])
+            co_a = _median([x[0] for x in res["co"]])
+            co_b = _median([x[1] for x in res["co"]])
+            sa, sb = _median(res["solo_a"]), _median(res["solo_b"])
+            out[f"D{D}_A{wa}_B{wb}"] = {
+                "depth": D, "waves": [wa, wb], "co_a_gbps": co_a, "co_b_gbps": co_b,
+                "solo_a_gbps": sa, "solo_b_gbps": sb,
+                "displacement_a": 1 - co_a / sa, "displacement_b": 1 - co_b / sb}
     return out
 
 
@@ -352,7 +356,11 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
 
 
 # ----------------------------------------------- precision reduction (C5b)
-def precision_sum(payload_bytes=4 * GIB, n=10, waves_per_cu=32, seed=SEED_BASE + 5):
+def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(8, 12, 16, 24, 32),
+                  seed=SEED_BASE + 5):
+    """Streaming FP32 / BF16 / FP8 sums of N(0,1) payloads.  The occupancy
+    is tuned per payload type (median of 3 launches per choice), then n
+    launches are timed at the chosen occupancy."""
     import synth
     out = {}
     for kind, dt in (("f32", isw.F32), ("bf16", isw.BF16), ("fp8_e4m3", isw.FP8_E4M3)):
@@ -360,14 +368,21 @@ def precision_sum(payload_bytes=4 * GIB, n=10, waves_per_cu=32, seed=SEED_BASE +
         n_el = payload_bytes // eb
         p = synth.normal_payload(kind, n_el, seed, device="cuda")
         torch.cuda.synchronize()
-        isw.sweep_reduce_fp(p, n_el, dt, waves_per_cu)
+        isw.sweep_reduce_fp(p, n_el, dt, waves_choices[0])
+        tune = {}
+        for w in waves_choices:
+            tune[w] = _median([isw.sweep_reduce_fp(p, n_el, dt, w)[1]["gbps"]
+                               for _ in range(3)])
+        best_w = max(tune, key=tune.get)
         gs, sums = [], []
         for _ in range(n):
-            s, r = isw.sweep_reduce_fp(p, n_el, dt, waves_per_cu)
+            s, r = isw.sweep_reduce_fp(p, n_el, dt, best_w)
             gs.append(r["gbps"])
             sums.append(s)
         out[kind] = {"elements": n_el, "sum": sums[0],
                      "deterministic": len(set(sums)) == 1,
+                     "waves_per_cu": best_w,
+                     "tuning_gbps": {w: round(g, 1) for w, g in tune.items()},
                      "median_gbps": _median(gs),
                      "frac_of_hbm_peak": _median(gs) / stats.HBM_PEAK_GBPS}
         del p

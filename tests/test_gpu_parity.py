@@ -412,8 +412,8 @@ def test_sweep_drivers_run_small():
     assert out["checksums_consistent"] and set(out["curves"]) == {4, 32}
     pc = sweeps.path_comparison(buf, nbytes, nbytes // 16, depths=(1, 4), waves_list=(1, 4), n=1)
     assert pc["checksums_equal_across_paths"] and pc[4][4]["ratio"] > 0
-    ts = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), n=1)
-    assert 4 in ts
+    ts = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((4, 4), (1, 2)), n=1)
+    assert set(ts) == {"D4_A4_B4", "D4_A1_B2"}
     al = sweeps.allocation_sweep([1 << 20, 4 << 20], Ks=(1, 2), waves_list=(8,), L=1 << 20, n=1)
     assert all(v["checksums_consistent"] for v in al.values())
     of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
