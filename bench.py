@@ -149,7 +149,7 @@ def main():
 
     from paper_2608_15764_amd import environment
     torch.cuda.set_device(0)
-    env_before = environment.amd_smi_metrics()
+    env_before = environment.sysfs_metrics()
     info = isw.sweep_device_info()
     hz = isw.sweep_calibrate_clock(0.5)
     policy = isw.POLICY_NAMES[a.policy]
@@ -193,7 +193,7 @@ def main():
     t1 = time.perf_counter()
     runs = [isw.result_dicts(r) for r in raws]
 
-    env_after = environment.amd_smi_metrics()
+    env_after = environment.sysfs_metrics()
     step_bytes = sum(r["issued_bytes"] for r in runs[0])
     value = a.steps * step_bytes / (t1 - t0) / 1e9
     kernel_ms = sum(r["event_ms"] for run in runs for r in run)
@@ -255,7 +255,7 @@ def main():
         "device": {"arch": info["arch"], "cus": info["num_cus"],
                    "clock_hz_calibrated": hz},
         "environment": {"static": environment.static_info(),
-                        "amd_smi_before": env_before, "amd_smi_after": env_after},
+                        "gpu_before": env_before, "gpu_after": env_after},
     }
     if not a.no_extras:
         # one untimed pass of the same sweep under every cache policy

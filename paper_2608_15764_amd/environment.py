@@ -3,51 +3,80 @@
 The method records driver, runtime, clocks, power limit and throttle state
 for every session and checks that no throttling happened during collection
 (Section 3, "Environment").  This module collects the same facts on the
-MI355X host: runtime versions, the host CPU, and a flattened subset of
-``amd-smi metric`` (clocks, power, temperature, throttle / violation
-counters), taken before and after a session so a changing clock or a
-throttle event is visible beside the numbers.
+MI355X host: runtime versions, the host CPU, and the GPU's current shader
+and memory clock levels, power, power cap, temperatures and performance
+level from sysfs, taken before and after a session so that a clock change
+is visible beside the numbers.  Everything is read from files; no helper
+program is started from the measuring process.
 """
-import json
 import os
 import platform
-import shutil
-import subprocess
 
-KEEP = ("clk", "clock", "power", "temp", "throttle", "violation", "socket_power",
-        "gfx_activity", "umc_activity", "ecc")
+def _read(path):
+    try:
+        with open(path) as f:
+            return f.read().strip()
+    except OSError:
+        return None
 
 
-def _flatten(obj, prefix="", out=None):
-    out = {} if out is None else out
-    if isinstance(obj, dict):
-        for k, v in obj.items():
-            _flatten(v, f"{prefix}.{k}" if prefix else str(k), out)
-    elif isinstance(obj, list):
-        for i, v in enumerate(obj):
-            _flatten(v, f"{prefix}[{i}]", out)
-    else:
-        out[prefix] = obj
+def _current_level(text):
+    """The level marked current ('*') in a pp_dpm_* table, e.g. '2400Mhz'."""
+    if not text:
+        return None
+    for line in text.splitlines():
+        if line.rstrip().endswith("*"):
+            return line.split(":", 1)[-1].replace("*", "").strip()
+    return None
+
+
+def gpu_devices(root="/sys/class/drm"):
+    """sysfs device directories of AMD GPUs (PCI vendor 0x1002)."""
+    out = []
+    try:
+        names = sorted(os.listdir(root))
+    except OSError:
+        return out
+    for n in names:
+        if not n.startswith("card") or "-" in n:
+            continue
+        d = os.path.join(root, n, "device")
+        if _read(os.path.join(d, "vendor")) == "0x1002":
+            out.append(d)
     return out
 
 
-def amd_smi_metrics(timeout=30, limit=80):
-    """Selected flattened ``amd-smi metric --json`` fields, or an error."""
-    exe = shutil.which("amd-smi") or "/opt/rocm/bin/amd-smi"
-    if not os.path.exists(exe):
-        return {"error": "amd-smi not found"}
+def sysfs_metrics(device_dir=None):
+    """Clocks, power, temperatures and performance level read from sysfs
+    (plain file reads: no helper program is started)."""
+    devs = [device_dir] if device_dir else gpu_devices()
+    if not devs:
+        return {"error": "no AMD GPU in sysfs"}
+    d = devs[0]
+    m = {"device": d,
+         "sclk": _current_level(_read(os.path.join(d, "pp_dpm_sclk"))),
+         "mclk": _current_level(_read(os.path.join(d, "pp_dpm_mclk"))),
+         "perf_level": _read(os.path.join(d, "power_dpm_force_performance_level")),
+         "link": _read(os.path.join(d, "current_link_speed"))}
+    hw = os.path.join(d, "hwmon")
     try:
-        r = subprocess.run([exe, "metric", "--json"], capture_output=True, text=True,
-                           timeout=timeout)
-    except (OSError, subprocess.TimeoutExpired) as e:
-        return {"error": f"amd-smi failed: {e}"}
-    try:
-        flat = _flatten(json.loads(r.stdout))
-    except ValueError:
-        return {"error": "amd-smi output is not JSON", "rc": r.returncode}
-    keep = {k: v for k, v in flat.items()
-            if any(t in k.lower() for t in KEEP) and v not in (None, "N/A", "")}
-    return dict(list(keep.items())[:limit])
+        hws = sorted(os.listdir(hw))
+    except OSError:
+        hws = []
+    for h in hws:
+        base = os.path.join(hw, h)
+        for f, key, scale in (("power1_input", "power_w", 1e-6),
+                              ("power1_average", "power_avg_w", 1e-6),
+                              ("power1_cap", "power_cap_w", 1e-6)):
+            v = _read(os.path.join(base, f))
+            if v is not None and v.lstrip("-").isdigit():
+                m[key] = int(v) * scale
+        for i in range(1, 6):
+            v = _read(os.path.join(base, f"temp{i}_input"))
+            if v is not None and v.lstrip("-").isdigit():
+                label = _read(os.path.join(base, f"temp{i}_label")) or f"temp{i}"
+                m[f"temp_{label}_c"] = int(v) / 1000.0
+    return m
 
 
 def cpu_model():
