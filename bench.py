@@ -257,6 +257,13 @@ def main():
         "environment": {"static": environment.static_info(),
                         "gpu_before": env_before, "gpu_after": env_after},
     }
+    # the same sweep as one hipGraph launch (kernel nodes only, per-cell
+    # clock windows, one event pair around the whole graph)
+    isw.sweep_batched(arr, raw=True)
+    graph_ms = sorted(isw.sweep_batched(arr, raw=True)[1] for _ in range(3))[1]
+    result["graph_sweep"] = {"cells": len(cells), "graph_ms": round(graph_ms, 3),
+                             "aggregate_gbps": round(step_bytes / (graph_ms * 1e6), 1),
+                             "timed_step_ms": result["ms_per_step"]}
     if not a.no_extras:
         # one untimed pass of the same sweep under every cache policy
         pc = {}
