@@ -94,6 +94,8 @@ def parse():
                     help="launch manifest path for --only c3counters")
     ap.add_argument("--json-out", default=None,
                     help="also write the full result to this file")
+    ap.add_argument("--record", default=None,
+                    help="append one JSON line per timed launch (raw log) to this file")
     return ap.parse_args()
 
 
@@ -192,6 +194,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     runs = [isw.result_dicts(r) for r in raws]
+    if a.record:
+        sweeps.write_records(a.record, meta, runs,
+                             {"policy": a.policy, "buffer_bytes": nbytes, "L": L})
 
     env_after = environment.sysfs_metrics()
     step_bytes = sum(r["issued_bytes"] for r in runs[0])
@@ -278,6 +283,8 @@ def main():
                         "paper_like_median_gbps": {k: round(v, 1) for k, v in
                                                    c16.get("median_gbps", {}).items()}}
         result["policy_curves"] = pc
+        result["baseline_fixed_iterations"] = sweeps.fixed_iteration_arm(buf, nbytes)
+        result["streaming_gate"] = sweeps.streaming_gate(buf, nbytes)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, 2, best_w, buf)
     del buf

@@ -557,3 +557,65 @@ def latency_ladder(footprints=None, stride=128, hops=8192, n_samples=4096,
     del evict_buf
     torch.cuda.empty_cache()
     return out
+
+
+# ------------------------------- baseline arm and streaming gate (Table 1)
+def fixed_iteration_arm(buf, nbytes, Ks=(1, 2, 4, 8), waves_per_cu=16, iters=None,
+                        policy=isw.CACHE_BYPASS_L1_NT, n=3):
+    """The paper's baseline arm (Section 4.2, Table 1, first row): every wave
+    runs the same iteration count at every K, so issued work grows with K.
+    ``iters`` defaults to one pass of the buffer at K = 1."""
+    info = isw.sweep_device_info()
+    n_waves = info["num_cus"] * waves_per_cu
+    if iters is None:
+        iters = max(1, nbytes // 16 // (64 * n_waves))
+    cells, meta = [], []
+    for direction in ("asc", "rev"):
+        ks = list(Ks) if direction == "asc" else list(reversed(list(Ks)))
+        for K in ks:
+            cells.append(isw.make_cell(buf, nbytes, K, 16, waves_per_cu, 0,
+                                       cache_policy=policy, mode=isw.FIXED_ITERS,
+                                       fixed_iters=iters))
+            meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K})
+    arr = isw.cell_array(cells)
+    isw.sweep_run(arr, raw=True)
+    runs = [isw.sweep_run(arr) for _ in range(n)]
+    summ = summarize_k_sweep(meta, runs)
+    c = summ["curves"][waves_per_cu]
+    issued = {m["K"]: r["issued_bytes"] for m, r in zip(meta, runs[0])}
+    return {"iters_per_wave": iters, "issued_bytes": issued,
+            "median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+            "decline_2_8": c.get("decline_2_8"), "by_order": c["by_order"]}
+
+
+def streaming_gate(buf, nbytes, vec_width=4, K=1, waves_per_cu=32, launches=31,
+                   policy=isw.CACHE_BYPASS_L1_NT):
+    """The streaming-read ceiling row of Section 4.1 ("read, 4 B width, ILP
+    1"): median and best of ``launches`` one-pass launches, as a fraction
+    of the HBM datasheet figure."""
+    c = isw.make_cell(buf, nbytes, K, vec_width, waves_per_cu, nbytes // vec_width,
+                      cache_policy=policy)
+    arr = isw.cell_array([c] * (launches + 1))
+    res = isw.sweep_run(arr)[1:]
+    g = sorted(r["gbps"] for r in res)
+    med = stats.median(g)
+    return {"vec_width": vec_width, "K": K, "waves_per_cu": waves_per_cu,
+            "launches": launches, "median_gbps": round(med, 1),
+            "best_gbps": round(g[-1], 1),
+            "median_frac": med / stats.HBM_PEAK_GBPS,
+            "best_frac": g[-1] / stats.HBM_PEAK_GBPS}
+
+
+def write_records(path, meta, runs, extra=None):
+    """Append one JSON line per launch (cell, pass index, raw result): the
+    raw log kept beside the reported medians."""
+    with open(path, "a") as f:
+        for i, run in enumerate(runs):
+            for m, r in zip(meta, run):
+                rec = dict(m)
+                rec["pass"] = i
+                rec.update({k: r[k] for k in ("issued_bytes", "sum32", "xor32", "gbps",
+                                              "window_ns", "event_ms", "waves")})
+                if extra:
+                    rec.update(extra)
+                f.write(json.dumps(rec) + "\n")

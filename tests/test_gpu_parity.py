@@ -423,3 +423,7 @@ def test_sweep_drivers_run_small():
     assert lad[8 << 10]["default"]["mean_ns"] > 0
     ps = sweeps.precision_sum(payload_bytes=1 << 20, n=2)
     assert all(v["deterministic"] for v in ps.values())
+    fi = sweeps.fixed_iteration_arm(buf, nbytes, Ks=(1, 2), waves_per_cu=8, n=1)
+    assert fi["issued_bytes"][2] == 2 * fi["issued_bytes"][1]
+    sg = sweeps.streaming_gate(buf, nbytes, launches=3)
+    assert sg["best_gbps"] >= sg["median_gbps"] > 0

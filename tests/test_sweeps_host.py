@@ -1,0 +1,47 @@
+"""Host-side helpers of the sweep drivers (no GPU)."""
+import json
+
+from paper_2608_15764_amd import sweeps
+
+
+def test_point_sizes_span_1MiB_to_2GiB_aligned():
+    s = sweeps.point_sizes(64)
+    assert len(s) == 64 and s[0] == 1 << 20 and s[-1] == 2 << 30
+    assert all(x % (64 * 1024) == 0 for x in s)
+    assert all(b >= a for a, b in zip(s, s[1:]))
+
+
+def test_size_classes():
+    M = 1 << 20
+    assert [sweeps.size_class(x) for x in (M, 4 * M, 20 * M, 100 * M, 300 * M, 2 << 30)] == \
+        [0, 1, 2, 3, 4, 5]
+
+
+def test_raw_records_roundtrip(tmp_path):
+    meta = [{"waves_per_cu": 16, "order": "asc", "K": 1}, {"waves_per_cu": 16, "order": "asc", "K": 2}]
+    r = {"issued_bytes": 1, "sum32": 2, "xor32": 3, "gbps": 4.0, "window_ns": 5.0,
+         "event_ms": 6.0, "waves": 7}
+    p = tmp_path / "raw.jsonl"
+    sweeps.write_records(str(p), meta, [[r, r], [r, r]], {"policy": "nt"})
+    lines = [json.loads(l) for l in open(p)]
+    assert len(lines) == 4 and lines[3]["pass"] == 1 and lines[1]["K"] == 2
+    assert lines[0]["policy"] == "nt" and lines[0]["gbps"] == 4.0
+
+
+def test_summarize_k_sweep_on_synthetic_results():
+    meta, runs = [], [[], []]
+    for order in ("asc", "rev"):
+        for K in ((1, 2, 4, 8) if order == "asc" else (8, 4, 2, 1)):
+            meta.append({"waves_per_cu": 16, "order": order, "K": K})
+    base = {1: 5000.0, 2: 7000.0, 4: 7100.0, 8: 7050.0}
+    for p in range(2):
+        for m in meta:
+            runs[p].append({"gbps": base[m["K"]] + p, "issued_loads": 1 << 26,
+                            "issued_bytes": 1 << 30, "sum32": 9, "xor32": 9,
+                            "waves": 4096})
+    s = sweeps.summarize_k_sweep(meta, runs)
+    c = s["curves"][16]
+    assert c["peak_K"] == 4 and s["checksums_consistent"]
+    assert abs(c["decline_2_8"] - (7050.5 - 7000.5) / 7000.5) < 1e-12
+    assert s["kset_mismatch"] == 0.0 and s["residency_flags"] == 0
+    assert c["in_flight_bytes"][2] == 4096 * 64 * 2 * 16
