@@ -427,3 +427,21 @@ def test_sweep_drivers_run_small():
     assert fi["issued_bytes"][2] == 2 * fi["issued_bytes"][1]
     sg = sweeps.streaming_gate(buf, nbytes, launches=3)
     assert sg["best_gbps"] >= sg["median_gbps"] > 0
+
+
+def test_graph_replays_match_eager_runs():
+    """Several graph launches with eager work and synchronisation between
+    them; every replay must reproduce the eager sinks."""
+    nbytes = 8 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 9)
+    cells = [isw.make_cell(buf, nbytes, K, 16, w, nbytes // 16, cache_policy=pol)
+             for K, w, pol in ((1, 4, 0), (2, 32, 3), (5, 16, 1), (16, 8, 2))]
+    cells.append(isw.make_cell(buf, nbytes, 6, 16, 2, nbytes // 16, kind=isw.KIND_LDS_ASYNC))
+    eager = [(r["sum32"], r["xor32"]) for r in isw.sweep_run(cells)]
+    for rep in range(4):
+        res, ms = isw.sweep_batched(cells)
+        assert [(r["sum32"], r["xor32"]) for r in res] == eager, rep
+        # eager work in between: a different cell set, then a sync
+        isw.sweep_plain(buf, nbytes, 3, 8, 12, nbytes // 8)
+        torch.cuda.synchronize()

@@ -130,3 +130,18 @@ def test_lds_matched_loop_goes_through_registers(lds, D):
     assert sum(l.startswith("ds_write_b128") for l in body) == D
     assert sum(l.startswith("ds_read_b128") for l in body) == D
     assert not any(l.startswith("global_load_lds") for l in body)
+
+
+def _kernel_names(text):
+    return re.findall(r"^\s+\.name:\s+(\S+)\s*$", text, re.M)
+
+
+@pytest.mark.parametrize("src", ["kernels_plain", "kernels_lds", "kernels_misc", "kernels_chase"])
+def test_no_kernel_spills_or_uses_scratch(src):
+    text = _asm(src)
+    names = [n for n in _kernel_names(text) if n.startswith("_Z")]
+    assert names, src
+    for n in names:
+        m = _meta(text, n)
+        assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0, n
+        assert m["private_segment_fixed_size"] == 0, n
