@@ -199,16 +199,24 @@ def attribute(rows, manifest, kernel_substr="plain_kload"):
     return out
 
 
+CELL_KEYS = ("bytes", "waves_per_cu", "K", "order")
+
+
+def cell_key(m):
+    """The cell a manifest entry belongs to (fields it has, in a fixed order)."""
+    return tuple(m[k] for k in CELL_KEYS if k in m)
+
+
 def cell_table(runs, manifest, fetch_scale=None):
-    """Per (bytes, K, order) cell: median of every counter over the
-    non-warm-up launches, plus the derived L2 hit rate and scaled bytes."""
+    """Per cell: median of every counter over the non-warm-up launches, plus
+    the derived L2 hit rate and scaled bytes."""
     cells = {}
     for rows in runs:
         for c, pairs in attribute(rows, manifest).items():
             for m, v in pairs:
                 if m["warmup"] or v is None:
                     continue
-                key = (m["bytes"], m["K"], m["order"])
+                key = cell_key(m)
                 cells.setdefault(key, {}).setdefault(c, []).append(v)
     table = {}
     for key, cs in sorted(cells.items()):
@@ -254,10 +262,11 @@ def main(argv=None):
         tab = cell_table([counter_rows(p) for p in a.counters], man, a.fetch_scale)
         lines = ["# rocprofv3 per-cell counters (generated by paper_2608_15764_amd.rocprof)"]
         lines += [f"# command: {c}" for c in a.command]
-        lines.append("# bytes K order: counter medians over non-warm-up launches")
-        for (b, K, o), row in tab.items():
+        keys = [k for k in CELL_KEYS if man and k in man[0]]
+        lines.append(f"# {' '.join(keys)}: counter medians over non-warm-up launches")
+        for key, row in tab.items():
             vals = " ".join(f"{c}={v:.6g}" for c, v in sorted(row.items()))
-            lines.append(f"{b} {K} {o}: {vals}")
+            lines.append(f"{' '.join(map(str, key))}: {vals}")
         text = "\n".join(lines) + "\n"
         if a.out:
             with open(a.out, "w") as f:

@@ -619,3 +619,28 @@ def write_records(path, meta, runs, extra=None):
                 if extra:
                     rec.update(extra)
                 f.write(json.dumps(rec) + "\n")
+
+
+def k_counter_pass(nbytes=GIB, waves_list=(4, 16), Ks=(1, 2, 4, 8, 16), L=1 << 26,
+                   policy=isw.CACHE_BYPASS_L1_NT, reps=3, seed=SEED_BASE + 1,
+                   manifest=None):
+    """The K sweep cell by cell, one launch per call, for a separate
+    rocprofv3 run with stall-reason and occupancy counters.  The first
+    launch of every cell is its warm-up.  Returns (and optionally writes)
+    the launch manifest."""
+    buf = device_buffer(nbytes, seed)
+    order = []
+    for w in waves_list:
+        for K in Ks:
+            c = isw.make_cell(buf, nbytes, K, 16, w, L, cache_policy=policy)
+            for rep in range(reps):
+                r = isw.sweep_run([c])[0]
+                order.append({"bytes": nbytes, "waves_per_cu": w, "K": K, "order": "asc",
+                              "rep": rep, "warmup": rep == 0,
+                              "issued_bytes": r["issued_bytes"], "gbps": r["gbps"]})
+    del buf
+    torch.cuda.empty_cache()
+    if manifest:
+        with open(manifest, "w") as f:
+            json.dump(order, f)
+    return order

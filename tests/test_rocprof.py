@@ -66,3 +66,30 @@ def test_missing_counter_gives_no_traffic(tmp_path):
     s = rocprof.summary(None, str(f), None, "plain_kload", 1 << 30)
     assert "hbm_bytes_per_launch" not in s
     assert s["fetch_failed_dispatches"] == 2
+
+
+def test_cell_table_keys_on_occupancy(tmp_path):
+    K4 = "void ilp::plain_kload<4, 16, 3>(ilp::PlainArgs)"
+    man = []
+    rows = []
+    for w in (4, 16):
+        for rep in range(3):
+            man.append({"bytes": 1 << 30, "waves_per_cu": w, "K": 4, "order": "asc",
+                        "rep": rep, "warmup": rep == 0})
+            rows.append((K4, "TCC_HIT_sum", 10.0 * w + rep))
+            rows.append((K4, "TCC_MISS_sum", 90.0))
+    # counters of one dispatch appear as consecutive rows with one dispatch id
+    p = tmp_path / "c_counter_collection.csv"
+    with open(p, "w", newline="") as f:
+        w_ = csv.DictWriter(f, fieldnames=CC_FIELDS)
+        w_.writeheader()
+        for i in range(len(man)):
+            for j in range(2):
+                k, c, v = rows[2 * i + j]
+                w_.writerow({"Dispatch_Id": i + 1, "Kernel_Name": k, "Grid_Size": 1,
+                             "Counter_Name": c, "Counter_Value": v})
+    tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man)
+    assert set(tab) == {(1 << 30, 4, 4, "asc"), (1 << 30, 16, 4, "asc")}
+    row = tab[(1 << 30, 4, 4, "asc")]
+    assert row["TCC_HIT_sum"] == 41.5                 # warm-up (40) excluded
+    assert row["l2_hit_rate"] == pytest.approx(41.5 / 131.5)
