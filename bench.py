@@ -190,15 +190,21 @@ def main():
     cells, meta = sweeps.plain_k_cells(buf, nbytes, L, policy, waves_list, Ks)
     cells, meta, dropped = sweeps.drop_infeasible(cells, meta)
 
+    # the step is one replay of the sweep captured once as a hipGraph: every
+    # kernel node sits between two captured event records, so each launch
+    # is still timed with hipEvents on the stream it runs on
     arr = isw.cell_array(cells)
+    graph = isw.sweep_graph_create(arr)
     for _ in range(a.warmup):
-        isw.sweep_run(arr, raw=True)
+        isw.sweep_graph_launch(graph, raw=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    raws = [isw.sweep_run(arr, raw=True) for _ in range(a.steps)]
+    outs = [isw.sweep_graph_launch(graph, raw=True) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    runs = [isw.result_dicts(r) for r in raws]
+    isw.sweep_graph_destroy(graph)
+    runs = [isw.result_dicts(r) for r, _ in outs]
+    graph_ms = sorted(ms for _, ms in outs)[len(outs) // 2]
     if a.record:
         sweeps.write_records(a.record, meta, runs,
                              {"policy": a.policy, "buffer_bytes": nbytes, "L": L})
@@ -267,13 +273,20 @@ def main():
         "environment": {"static": environment.static_info(),
                         "gpu_before": env_before, "gpu_after": env_after},
     }
-    # the same sweep as one hipGraph launch (kernel nodes only, per-cell
-    # clock windows, one event pair around the whole graph)
-    isw.sweep_batched(arr, raw=True)
-    graph_ms = sorted(isw.sweep_batched(arr, raw=True)[1] for _ in range(3))[1]
-    result["graph_sweep"] = {"cells": len(cells), "graph_ms": round(graph_ms, 3),
-                             "aggregate_gbps": round(step_bytes / (graph_ms * 1e6), 1),
-                             "timed_step_ms": result["ms_per_step"]}
+    # the same sweep launched eagerly, cell by cell (sweep_run): the cost of
+    # one host launch per kernel against the graph replay timed above
+    isw.sweep_run(arr, raw=True)
+    torch.cuda.synchronize()
+    eager = []
+    for _ in range(3):
+        e0 = time.perf_counter()
+        isw.sweep_run(arr, raw=True)
+        eager.append(time.perf_counter() - e0)
+    eager_ms = sorted(eager)[1] * 1e3
+    result["eager_sweep"] = {"cells": len(cells), "step_ms": round(eager_ms, 3),
+                             "aggregate_gbps": round(step_bytes / (eager_ms * 1e6), 1),
+                             "graph_step_ms": result["ms_per_step"],
+                             "graph_launch_event_ms": round(graph_ms, 3)}
     if not a.no_extras:
         # one untimed pass of the same sweep under every cache policy
         pc = {}

@@ -627,59 +627,151 @@ int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
   return run_prepared(*d, ps, as_stream(opt), nullptr, nullptr, results);
 }
 
+}  // extern "C"
+
+// A captured sweep with its own scratch (see sweep_graph_create).
+struct sweep_graph {
+  int ordinal = -1;
+  std::vector<Prepared> ps;
+  sweep_wave_rec_t* rec = nullptr;
+  CellRes* res = nullptr;
+  CellRes* res_h = nullptr;
+  uint64_t* offs = nullptr;
+  std::vector<hipEvent_t> ev;   // 2 per cell, then start, end, done
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_graph(sweep_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (auto e : g->ev) (void)hipEventDestroy(e);
+  if (g->rec) (void)hipFree(g->rec);
+  if (g->res) (void)hipFree(g->res);
+  if (g->offs) (void)hipFree(g->offs);
+  if (g->res_h) (void)hipHostFree(g->res_h);
+  delete g;
+}
+
+int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
+                 sweep_graph** out) {
+  sweep_graph* g = new sweep_graph();
+  g->ordinal = d.ordinal;
+  g->ps.resize((size_t)n);
+  int rc = SWEEP_OK;
+  for (int i = 0; i < n && rc == SWEEP_OK; ++i)
+    rc = prepare(d, cells[i], pin_of(opt), &g->ps[(size_t)i]);
+  if (rc != SWEEP_OK) {
+    free_graph(g);
+    return rc;
+  }
+  const std::vector<uint64_t> offs = record_offsets(g->ps);
+  auto fail_g = [&](int code, const std::string& msg) {
+    free_graph(g);
+    return fail(code, msg);
+  };
+  const size_t n_rec = std::max<uint64_t>(offs.back(), 1);
+  if (hipMalloc(reinterpret_cast<void**>(&g->rec), n_rec * sizeof(sweep_wave_rec_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&g->res), (size_t)n * sizeof(CellRes)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&g->offs), offs.size() * sizeof(uint64_t)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&g->res_h), (size_t)n * sizeof(CellRes), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail_g(SWEEP_ENOMEM, "graph scratch allocation failed");
+  }
+  if (hipMemcpy(g->offs, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail_g(SWEEP_EHIP, "graph offsets upload failed");
+  g->ev.resize(2 * (size_t)n + 3, nullptr);
+  for (auto& e : g->ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail_g(SWEEP_EHIP, "hipEventCreate failed");
+  if (!d.capture && hipStreamCreateWithFlags(&d.capture, hipStreamNonBlocking) != hipSuccess)
+    return fail_g(SWEEP_EHIP, "capture stream creation failed");
+  if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail_g(SWEEP_EHIP, "hipStreamBeginCapture failed");
+  hipError_t cap_err = hipSuccess;
+  for (int i = 0; i < n && cap_err == hipSuccess; ++i)
+    cap_err = enqueue(g->ps[(size_t)i], d.capture, g->rec + offs[(size_t)i], nullptr,
+                      g->ev[2 * (size_t)i], g->ev[2 * (size_t)i + 1]);
+  if (cap_err == hipSuccess)
+    cap_err = launch_finish_cells(g->rec, g->offs, (uint32_t)n, g->res, d.capture);
+  hipError_t end_err = hipStreamEndCapture(d.capture, &g->graph);
+  if (cap_err != hipSuccess || end_err != hipSuccess)
+    return fail_g(SWEEP_EHIP, std::string("graph capture failed: ") +
+                                  hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+  hipError_t ie = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess)
+    return fail_g(SWEEP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  *out = g;
+  return SWEEP_OK;
+}
+
+int launch_graph(Dev& d, sweep_graph* g, hipStream_t st, sweep_result_t* results,
+                 double* graph_ms) {
+  const size_t n = g->ps.size();
+  hipEvent_t e_start = g->ev[2 * n], e_end = g->ev[2 * n + 1], e_done = g->ev[2 * n + 2];
+  HIP_TRY(hipEventRecord(e_start, st));
+  HIP_TRY(hipGraphLaunch(g->exec, st));
+  HIP_TRY(hipEventRecord(e_end, st));
+  HIP_TRY(hipMemcpyAsync(g->res_h, g->res, n * sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(e_done, st));
+  HIP_TRY(hipEventSynchronize(e_done));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e_start, e_end));
+  if (graph_ms) *graph_ms = ms;
+  for (size_t i = 0; i < n; ++i) {
+    float cms = 0;
+    HIP_TRY(hipEventElapsedTime(&cms, g->ev[2 * i], g->ev[2 * i + 1]));
+    fill_result(d, g->ps[i], g->res_h[i], cms, &results[i]);
+  }
+  return SWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sweep_graph_create(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
+                       sweep_graph_t** out) {
+  if (!cells || !out || n <= 0) return fail(SWEEP_EINVAL, "empty cell list");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  return create_graph(*d, cells, n, opt, out);
+}
+
+int sweep_graph_launch(sweep_graph_t* graph, void* stream, sweep_result_t* results,
+                       double* graph_ms) {
+  if (!graph || !results) return fail(SWEEP_EINVAL, "NULL graph or results");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(init_device(graph->ordinal, &d));
+  return launch_graph(*d, graph, static_cast<hipStream_t>(stream), results, graph_ms);
+}
+
+int sweep_graph_destroy(sweep_graph_t* graph) {
+  if (!graph) return SWEEP_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(graph->ordinal);
+  free_graph(graph);
+  (void)hipSetDevice(cur);
+  return SWEEP_OK;
+}
+
 int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
                   sweep_result_t* results, double* graph_ms) {
   if (!cells || !results || n <= 0) return fail(SWEEP_EINVAL, "empty cell list");
   std::lock_guard<std::mutex> lk(g_mu);
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
-  std::vector<Prepared> ps((size_t)n);
-  for (int i = 0; i < n; ++i) SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
-  const std::vector<uint64_t> offs = record_offsets(ps);
-  SW_TRY(ensure_dev(d->rec, d->rec_cap, offs[(size_t)n]));
-  SW_TRY(ensure_dev(d->res, d->res_cap, (size_t)n));
-  SW_TRY(ensure_host(d->res_h, d->res_h_cap, (size_t)n));
-  SW_TRY(ensure_events(*d, 3));
-  hipStream_t st = as_stream(opt);
-  // the offsets are uploaded before capture: the graph holds kernels only
-  SW_TRY(upload_offsets(*d, offs, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (!d->capture) HIP_TRY(hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking));
-  hipGraph_t graph = nullptr;
-  HIP_TRY(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
-  hipError_t cap_err = hipSuccess;
-  for (int i = 0; i < n && cap_err == hipSuccess; ++i)
-    cap_err = enqueue(ps[(size_t)i], d->capture, d->rec + offs[(size_t)i], nullptr,
-                      nullptr, nullptr);
-  if (cap_err == hipSuccess)
-    cap_err = launch_finish_cells(d->rec, d->offs, (uint32_t)n, d->res, d->capture);
-  hipError_t end_err = hipStreamEndCapture(d->capture, &graph);
-  if (cap_err != hipSuccess || end_err != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return fail(SWEEP_EHIP, std::string("graph capture failed: ") +
-                                hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
-  }
-  hipGraphExec_t exec = nullptr;
-  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (ie != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return fail(SWEEP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-  }
-  hipError_t le = hipEventRecord(d->ev[0], st);
-  if (le == hipSuccess) le = hipGraphLaunch(exec, st);
-  if (le == hipSuccess) le = hipEventRecord(d->ev[1], st);
-  if (le == hipSuccess)
-    le = hipMemcpyAsync(d->res_h, d->res, (size_t)n * sizeof(CellRes), hipMemcpyDeviceToHost, st);
-  if (le == hipSuccess) le = hipEventRecord(d->ev[2], st);
-  if (le == hipSuccess) le = hipEventSynchronize(d->ev[2]);
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  if (le != hipSuccess) return fail(SWEEP_EHIP, std::string("graph launch: ") + hipGetErrorString(le));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
-  if (graph_ms) *graph_ms = ms;
-  for (int i = 0; i < n; ++i) fill_result(*d, ps[(size_t)i], d->res_h[i], 0.0, &results[i]);
-  return SWEEP_OK;
+  sweep_graph* g = nullptr;
+  SW_TRY(create_graph(*d, cells, n, opt, &g));
+  const int rc = launch_graph(*d, g, as_stream(opt), results, graph_ms);
+  free_graph(g);
+  return rc;
 }
 
 int sweep_autotune(const void* buf, size_t bytes, const int* vec_widths,

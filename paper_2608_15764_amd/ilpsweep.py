@@ -128,6 +128,11 @@ _SIG = {
                                 C.POINTER(sweep_opts_t),
                                 C.POINTER(sweep_result_t),
                                 C.POINTER(C.c_double)]),
+    "sweep_graph_create": (C.c_int, [C.POINTER(sweep_cell_t), C.c_int,
+                                     C.POINTER(sweep_opts_t), C.POINTER(_P)]),
+    "sweep_graph_launch": (C.c_int, [_P, _P, C.POINTER(sweep_result_t),
+                                     C.POINTER(C.c_double)]),
+    "sweep_graph_destroy": (C.c_int, [_P]),
     "sweep_autotune": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_int), C.c_int,
                                  C.POINTER(C.c_int), C.c_int,
                                  C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int,
@@ -330,6 +335,37 @@ def sweep_batched(cells, opts=None, raw=False):
     _check(lib.sweep_batched(arr, len(arr), C.byref(o), res, C.byref(ms)),
            "sweep_batched")
     return (res if raw else result_dicts(res)), ms.value
+
+
+class SweepGraph:
+    """Handle of a captured sweep: the C handle and its cell count."""
+
+    def __init__(self, handle, n):
+        self.handle = handle
+        self.n = n
+
+
+def sweep_graph_create(cells, opts=None):
+    arr = cell_array(cells)
+    h = _P()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_graph_create(arr, len(arr), C.byref(o), C.byref(h)),
+           "sweep_graph_create")
+    return SweepGraph(h.value, len(arr))
+
+
+def sweep_graph_launch(graph, stream=None, raw=False):
+    res = (sweep_result_t * graph.n)()
+    ms = C.c_double()
+    _check(lib.sweep_graph_launch(graph.handle, _stream(stream), res,
+                                  C.byref(ms)), "sweep_graph_launch")
+    return (res if raw else result_dicts(res)), ms.value
+
+
+def sweep_graph_destroy(graph):
+    if graph is not None and graph.handle:
+        _check(lib.sweep_graph_destroy(graph.handle), "sweep_graph_destroy")
+        graph.handle = None
 
 
 def sweep_autotune(buf, bytes_, vec_widths, Ks, waves_per_cu,

@@ -1,6 +1,7 @@
 /* Plain-C user of the C ABI: no torch, no Python.  Allocates a buffer with
  * the HIP runtime, fills it with the seeded generator, runs one plain-load
- * cell, one LDS-direct cell and one graph-batched pair, and prints the
+ * cell, one LDS-direct cell, one graph-batched pair and two replays of a
+ * captured graph (the buffer refilled with seed + 1 between them), and prints the
  * global sinks as "name sum xor issued" lines for the calling test to check
  * against the oracle. */
 #include <stdio.h>
@@ -55,6 +56,16 @@ int main(int argc, char** argv) {
   for (int i = 0; i < 2; ++i)
     printf("batched_K%d %u %u %llu\n", cells[i].K, rs[i].sum32, rs[i].xor32,
            (unsigned long long)rs[i].issued_loads);
+  sweep_graph_t* g = NULL;
+  CHECK(sweep_graph_create(cells, 2, &opt, &g));
+  for (int rep = 0; rep < 2; ++rep) {
+    if (rep) CHECK(sweep_fill_u32(buf, bytes, seed + 1, NULL));
+    CHECK(sweep_graph_launch(g, NULL, rs, &ms));
+    for (int i = 0; i < 2; ++i)
+      printf("graph_K%d_rep%d %u %u %llu\n", cells[i].K, rep, rs[i].sum32, rs[i].xor32,
+             (unsigned long long)rs[i].issued_loads);
+  }
+  CHECK(sweep_graph_destroy(g));
   CHECK(sweep_shutdown());
   (void)hipFree(buf);
   return 0;

@@ -45,3 +45,10 @@ def test_plain_c_program(tmp_path):
     p = oplan.wave_group(L, 3, n_waves)
     want = checksums.combine(*checksums.per_wave(words, 16, 3, p["Q"], n_waves))
     assert res["batched_K3"] == (*want, p["issued"])
+    # a captured graph replays against the buffer's current contents
+    assert res["graph_K3_rep0"] == res["batched_K3"]
+    assert res["graph_K2_rep0"][:2] == whole
+    words1 = splitmix.buffer_words(seed + 1, nbytes)
+    assert res["graph_K2_rep1"] == (*checksums.whole_buffer(words1), L)
+    want1 = checksums.combine(*checksums.per_wave(words1, 16, 3, p["Q"], n_waves))
+    assert res["graph_K3_rep1"] == (*want1, p["issued"])

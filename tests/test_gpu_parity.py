@@ -401,6 +401,17 @@ def test_window_agrees_with_events():
         ev_ns = r["event_ms"] * 1e6
         assert 0.85 < r["window_ns"] / ev_ns <= 1.02, (r["window_ns"], ev_ns)
         assert abs(r["gbps"] - r["issued_bytes"] / r["window_ns"]) < 1e-6
+        # the same through a graph: events captured around each kernel node
+        g = isw.sweep_graph_create([isw.make_cell(buf, nbytes, 4, 16, w, nbytes // 16)] * 3)
+        try:
+            for _ in range(2):
+                res, ms = isw.sweep_graph_launch(g)
+            for r in res:
+                ev_ns = r["event_ms"] * 1e6
+                assert 0.85 < r["window_ns"] / ev_ns <= 1.02, (r["window_ns"], ev_ns)
+            assert 0.9 < sum(r["event_ms"] for r in res) / ms < 1.1
+        finally:
+            isw.sweep_graph_destroy(g)
 
 
 def test_sweep_drivers_run_small():
@@ -445,3 +456,49 @@ def test_graph_replays_match_eager_runs():
         # eager work in between: a different cell set, then a sync
         isw.sweep_plain(buf, nbytes, 3, 8, 12, nbytes // 8)
         torch.cuda.synchronize()
+
+
+def test_persistent_graph_replays():
+    """A graph captured once: every replay reads the buffer's current
+    contents, keeps its own scratch across other library calls, and times
+    each kernel with its captured events."""
+    nbytes = 8 << 20
+    buf = dev_bytes(nbytes)
+    other = dev_bytes(nbytes)
+    isw.sweep_fill_u32(other, nbytes, SEED + 21)
+    cells = [isw.make_cell(buf, nbytes, K, 16, w, nbytes // 16, cache_policy=pol)
+             for K, w, pol in ((1, 4, 3), (3, 32, 0), (7, 16, 2), (16, 8, 1))]
+    cells.append(isw.make_cell(buf, nbytes, 4, 16, 4, nbytes // 16, kind=isw.KIND_LDS_MATCHED))
+    g = isw.sweep_graph_create(cells)
+    try:
+        for rep in range(4):
+            seed = SEED + 30 + rep
+            isw.sweep_fill_u32(buf, nbytes, seed)
+            torch.cuda.synchronize()
+            res, ms = isw.sweep_graph_launch(g)
+            words = splitmix.buffer_words(seed, nbytes)
+            for c, r in zip(cells, res):
+                n_waves = r["waves"]
+                p = oplan.wave_group(c.total_logical_loads, c.K, n_waves)
+                want = checksums.combine(*checksums.per_wave(words, 16, c.K, p["Q"], n_waves))
+                assert (r["sum32"], r["xor32"]) == want, (rep, c.K)
+                assert r["issued_loads"] == p["issued"]
+                assert 0 < r["window_ns"] <= r["event_ms"] * 1e6 + 2000
+            assert ms > 0
+            # other calls between replays reuse the library's shared scratch
+            isw.sweep_run([isw.make_cell(other, nbytes, 2, 16, 32, nbytes // 16)] * 3)
+            isw.sweep_batched([isw.make_cell(other, nbytes, 5, 8, 8, nbytes // 8)])
+    finally:
+        isw.sweep_graph_destroy(g)
+    isw.sweep_graph_destroy(g)          # a destroyed handle is cleared, not freed twice
+
+
+def test_persistent_graph_rejects_bad_cells():
+    nbytes = 1 << 20
+    buf = dev_bytes(nbytes)
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_graph_create([isw.make_cell(buf, nbytes, 17, 16, 4, nbytes // 16)])
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError):
+        isw.sweep_graph_create([])
+    assert isw.lib.sweep_graph_destroy(None) == isw.OK
