@@ -130,7 +130,7 @@ typedef struct {
   uint32_t vgprs, sgprs, lds_bytes, scratch_bytes; /* kernel resources     */
   uint64_t window_ticks;   /* max(t1) - min(t0) over all waves             */
   double   window_ns;      /* window_ticks converted with the clock rate   */
-  double   event_ms;       /* hipEvent elapsed around the kernel           */
+  double   event_ms;       /* hipEvent time of the kernel's dispatch       */
   double   gbps;           /* issued_bytes / window_ns                     */
 } sweep_result_t;
 
@@ -293,29 +293,28 @@ int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
               sweep_result_t* results);
 
 /* Batched sweep: the same cells captured into a hipGraph (one kernel node
- * per cell, each between two captured event records, then one finishing
- * node) and launched with a single hipGraphLaunch; equivalent to
- * sweep_graph_create + sweep_graph_launch + sweep_graph_destroy.
- * results[i].event_ms is the cell's kernel time from the captured events,
- * *graph_ms the hipEvent time of the whole launch.  Errors as sweep_run. */
+ * per cell, then one finishing node) and launched with a single
+ * hipGraphLaunch; equivalent to sweep_graph_create + sweep_graph_launch +
+ * sweep_graph_destroy.  Per-cell windows come from the in-kernel clock
+ * records; results[i].event_ms is 0 and *graph_ms receives the hipEvent
+ * time of the whole launch.  Errors as sweep_run. */
 int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
                   sweep_result_t* results, double* graph_ms);
 
-/* A sweep captured once into a hipGraph and replayed: the cells' kernels,
- * each between two event records captured in the graph (so every replay
- * still times every kernel with hipEvents), and one finishing kernel.  The
- * graph owns its scratch (wave records, per-cell results, offsets; about
- * 32 B per wave plus 32 B per cell), so other library calls between replays
- * do not disturb it.  The cells' buffers must stay allocated until the
- * graph is destroyed; their contents may change between replays.
+/* A sweep captured once into a hipGraph and replayed: one kernel node per
+ * cell, in order, then one finishing kernel.  The graph owns its scratch
+ * (wave records, per-cell results, offsets; 32 B per wave plus 40 B per
+ * cell), so other library calls between replays do not disturb it.  The
+ * cells' buffers must stay allocated until the graph is destroyed; their
+ * contents may change between replays.
  * sweep_graph_create: validates every cell (errors as sweep_run), captures
  *   and instantiates; *out receives the handle.  Only opt->pin_occupancy is
  *   read (opt may be NULL).  SWEEP_ENOMEM if the scratch cannot be had.
  * sweep_graph_launch: replays on `stream` (a hipStream_t of the graph's
  *   device, NULL = default stream), waits, and fills results[0..n) in cell
- *   order (event_ms from the captured events) and *graph_ms (hipEvent time
- *   of the whole replay; may be NULL).  Replays of one graph must not
- *   overlap.
+ *   order (per-cell windows from the in-kernel clock records, event_ms 0)
+ *   and *graph_ms (hipEvent time of the whole replay; may be NULL).
+ *   Replays of one graph must not overlap.
  * sweep_graph_destroy: frees the graph and its scratch; NULL is allowed. */
 typedef struct sweep_graph sweep_graph_t;
 int sweep_graph_create(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,

@@ -3,6 +3,7 @@
 // the caller's stream with hipEvents, per-cell finishing, the back-to-back
 // sweep driver, the hipGraph-batched sweep, the autotuner and the clock
 // calibration.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -230,24 +231,27 @@ int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   return SWEEP_OK;
 }
 
-// Records the optional events around the cell's kernel; the wave records
-// go to `rec`, which holds at least the cell's waves.
+// Launches the cell's kernel; the wave records go to `rec`, which holds at
+// least the cell's waves.  With events, hipExtLaunchKernel stamps them from
+// the kernel's own dispatch (its start and its end), with no marker packets
+// between kernels; without (under graph capture), a plain launch.
 hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
                    uint32_t* lane_out, hipEvent_t e0, hipEvent_t e1) {
-  hipError_t e = hipSuccess;
-  if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
+  PlainArgs pa{};
+  LdsArgs la{};
+  void* args[1];
   if (p.c.kind == SWEEP_KIND_PLAIN) {
-    PlainArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-                p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
-    e = launch_plain(p.c.K, p.c.vec_width, p.c.cache_policy, p.grid, p.lds, st, a);
+    pa = PlainArgs{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+                   p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
+    args[0] = &pa;
   } else {
-    LdsArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-              p.plan.stride, rec, lane_out, p.plan.wg_waves};
-    e = launch_lds(p.c.kind, p.c.K, p.c.cache_policy, p.grid, p.threads, p.lds, st, a);
+    la = LdsArgs{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+                 p.plan.stride, rec, lane_out, p.plan.wg_waves};
+    args[0] = &la;
   }
-  if (e != hipSuccess) return e;
-  if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
-  return hipSuccess;
+  if (e0 || e1)
+    return hipExtLaunchKernel(p.fn, dim3(p.grid), dim3(p.threads), args, p.lds, st, e0, e1, 0);
+  return hipLaunchKernel(p.fn, dim3(p.grid), dim3(p.threads), args, p.lds, st);
 }
 
 // Copies the record offsets of `n` cells (n + 1 entries) to the device.
@@ -637,7 +641,7 @@ struct sweep_graph {
   CellRes* res = nullptr;
   CellRes* res_h = nullptr;
   uint64_t* offs = nullptr;
-  std::vector<hipEvent_t> ev;   // 2 per cell, then start, end, done
+  std::vector<hipEvent_t> ev;   // start, end, done of a launch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -683,7 +687,7 @@ int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* o
   }
   if (hipMemcpy(g->offs, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
     return fail_g(SWEEP_EHIP, "graph offsets upload failed");
-  g->ev.resize(2 * (size_t)n + 3, nullptr);
+  g->ev.resize(3, nullptr);
   for (auto& e : g->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail_g(SWEEP_EHIP, "hipEventCreate failed");
   if (!d.capture && hipStreamCreateWithFlags(&d.capture, hipStreamNonBlocking) != hipSuccess)
@@ -693,7 +697,7 @@ int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* o
   hipError_t cap_err = hipSuccess;
   for (int i = 0; i < n && cap_err == hipSuccess; ++i)
     cap_err = enqueue(g->ps[(size_t)i], d.capture, g->rec + offs[(size_t)i], nullptr,
-                      g->ev[2 * (size_t)i], g->ev[2 * (size_t)i + 1]);
+                      nullptr, nullptr);
   if (cap_err == hipSuccess)
     cap_err = launch_finish_cells(g->rec, g->offs, (uint32_t)n, g->res, d.capture);
   hipError_t end_err = hipStreamEndCapture(d.capture, &g->graph);
@@ -710,7 +714,7 @@ int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* o
 int launch_graph(Dev& d, sweep_graph* g, hipStream_t st, sweep_result_t* results,
                  double* graph_ms) {
   const size_t n = g->ps.size();
-  hipEvent_t e_start = g->ev[2 * n], e_end = g->ev[2 * n + 1], e_done = g->ev[2 * n + 2];
+  hipEvent_t e_start = g->ev[0], e_end = g->ev[1], e_done = g->ev[2];
   HIP_TRY(hipEventRecord(e_start, st));
   HIP_TRY(hipGraphLaunch(g->exec, st));
   HIP_TRY(hipEventRecord(e_end, st));
@@ -720,11 +724,7 @@ int launch_graph(Dev& d, sweep_graph* g, hipStream_t st, sweep_result_t* results
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, e_start, e_end));
   if (graph_ms) *graph_ms = ms;
-  for (size_t i = 0; i < n; ++i) {
-    float cms = 0;
-    HIP_TRY(hipEventElapsedTime(&cms, g->ev[2 * i], g->ev[2 * i + 1]));
-    fill_result(d, g->ps[i], g->res_h[i], cms, &results[i]);
-  }
+  for (size_t i = 0; i < n; ++i) fill_result(d, g->ps[i], g->res_h[i], 0.0, &results[i]);
   return SWEEP_OK;
 }
 

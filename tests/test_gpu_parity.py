@@ -401,15 +401,13 @@ def test_window_agrees_with_events():
         ev_ns = r["event_ms"] * 1e6
         assert 0.85 < r["window_ns"] / ev_ns <= 1.02, (r["window_ns"], ev_ns)
         assert abs(r["gbps"] - r["issued_bytes"] / r["window_ns"]) < 1e-6
-        # the same through a graph: events captured around each kernel node
+        # the same through a graph: the kernels' windows fill the replay
         g = isw.sweep_graph_create([isw.make_cell(buf, nbytes, 4, 16, w, nbytes // 16)] * 3)
         try:
             for _ in range(2):
                 res, ms = isw.sweep_graph_launch(g)
-            for r in res:
-                ev_ns = r["event_ms"] * 1e6
-                assert 0.85 < r["window_ns"] / ev_ns <= 1.02, (r["window_ns"], ev_ns)
-            assert 0.9 < sum(r["event_ms"] for r in res) / ms < 1.1
+            frac = sum(r["window_ns"] for r in res) / (ms * 1e6)
+            assert 0.85 < frac <= 1.02, frac
         finally:
             isw.sweep_graph_destroy(g)
 
@@ -483,8 +481,8 @@ def test_persistent_graph_replays():
                 want = checksums.combine(*checksums.per_wave(words, 16, c.K, p["Q"], n_waves))
                 assert (r["sum32"], r["xor32"]) == want, (rep, c.K)
                 assert r["issued_loads"] == p["issued"]
-                assert 0 < r["window_ns"] <= r["event_ms"] * 1e6 + 2000
-            assert ms > 0
+                assert r["window_ns"] > 0 and r["event_ms"] == 0
+            assert 0 < sum(r["window_ns"] for r in res) <= ms * 1e6 * 1.02
             # other calls between replays reuse the library's shared scratch
             isw.sweep_run([isw.make_cell(other, nbytes, 2, 16, 32, nbytes // 16)] * 3)
             isw.sweep_batched([isw.make_cell(other, nbytes, 5, 8, 8, nbytes // 8)])
