@@ -100,39 +100,58 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(buf_seed, nbytes, L, K, waves_per_cu, gpu_buf):
-    """Oracle per-wave checksums of one full cell, timed on the host."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
+    """Oracle per-wave checksums of one occupancy's whole K curve (one full
+    cell per K), timed on the host and checked against the GPU's records."""
     import numpy as np
     import torch
     from oracle import checksums, plan as oplan, splitmix
     from paper_2608_15764_amd import ilpsweep as isw
 
-    rec = torch.zeros(256 * waves_per_cu * 32, dtype=torch.uint8, device="cuda")
-    r = isw.sweep_plain(gpu_buf, nbytes, K, 16, waves_per_cu, L,
-                        isw.make_opts(wave_out=rec))
     dt = np.dtype([("sum32", "<u4"), ("xor32", "<u4"), ("hw_id", "<u4"),
                    ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
-    recs = rec.cpu().numpy().view(dt)[: r["waves"]]
+    gpu = {}
+    for K in Ks:
+        rec = torch.zeros(256 * waves_per_cu * 32, dtype=torch.uint8, device="cuda")
+        r = isw.sweep_plain(gpu_buf, nbytes, K, 16, waves_per_cu, L,
+                            isw.make_opts(wave_out=rec))
+        gpu[K] = (r, rec.cpu().numpy().view(dt)[: r["waves"]])
     t0 = time.perf_counter()
     words = splitmix.buffer_words(buf_seed, nbytes)
     t1 = time.perf_counter()
-    p = oplan.wave_group(L, K, r["waves"])
-    s, x = checksums.per_wave(words, 16, K, p["Q"], r["waves"])
+    issued, ok = 0, True
+    for K in Ks:
+        r, recs = gpu[K]
+        p = oplan.wave_group(L, K, r["waves"])
+        s, x = checksums.per_wave(words, 16, K, p["Q"], r["waves"])
+        issued += p["issued"] * 16
+        ok = ok and bool(np.array_equal(s, recs["sum32"]) and np.array_equal(x, recs["xor32"])
+                         and p["issued"] == r["issued_loads"])
     t2 = time.perf_counter()
-    ok = bool(np.array_equal(s, recs["sum32"]) and np.array_equal(x, recs["xor32"])
-              and p["issued"] == r["issued_loads"])
     return {
-        "value": p["issued"] * 16 / (t2 - t1) / 1e9,
+        "value": issued / (t2 - t1) / 1e9,
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one full cell of the sweep: per-wave sum/xor checksums of "
-                   f"{p['issued'] * 16 >> 20} MiB issued (K={K}, "
-                   f"{waves_per_cu} waves/CU, {r['waves']} waves), NumPy, one "
+        "sample": (f"{len(Ks)} full cells of the sweep (K={Ks[0]}..{Ks[-1]} at "
+                   f"{waves_per_cu} waves/CU, {gpu[Ks[0]][0]['waves']} waves): per-wave "
+                   f"sum/xor checksums of {issued >> 30} GiB issued, NumPy, one "
                    f"process; buffer generation {t1 - t0:.1f} s excluded"),
         "checksum_s": t2 - t1,
         "generate_s": t1 - t0,
         "host_cores_available": os.cpu_count(),
+        "host_cpu": _cpu_model(),
         "matches_gpu": ok,
     }
 
@@ -256,6 +275,10 @@ def main():
             "peak_K": w4["peak_K"], "decline_2_8": w4.get("decline_2_8"),
             "regime": w4["regime"], "by_order": w4["by_order"]},
         "curves": {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                       "pct_of_best_cell": {k: round(100 * v / summ["peak_gbps"], 1)
+                                            for k, v in c["median_gbps"].items()},
+                       "littles_law_latency_ns": {k: round(v, 1) for k, v in
+                                                  c["implied_latency_ns"].items()},
                        "peak_K": c["peak_K"], "knee_K": c["knee_K"],
                        "regime": c["regime"], "decline_2_8": c.get("decline_2_8"),
                        "by_order": c["by_order"]}
@@ -313,7 +336,8 @@ def main():
         result["baseline_fixed_iterations"] = sweeps.fixed_iteration_arm(buf, nbytes)
         result["streaming_gate"] = sweeps.streaming_gate(buf, nbytes)
     if not a.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, 2, best_w, buf)
+        ks_best = sorted({m["K"] for m in meta if m["waves_per_cu"] == best_w})
+        result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf)
     del buf
     torch.cuda.empty_cache()
     if not a.no_extras:

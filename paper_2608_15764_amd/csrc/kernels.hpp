@@ -86,20 +86,15 @@ struct CellRes {
   uint64_t tmax;
 };
 
-// ---- plain (kernels_plain.hip)
+// ---- kernel lookup: the host launches these with their one argument
+// struct (PlainArgs, LdsArgs, TwoStreamArgs, ReduceArgs); nullptr for an
+// unknown combination.
+// plain (kernels_plain.hip)
 const void* plain_kernel(int K, int V, int policy);
-hipError_t launch_plain(int K, int V, int policy, uint32_t grid,
-                        size_t lds_bytes, hipStream_t st, const PlainArgs& a);
 
 // ---- LDS paths (kernels_lds.hip)
 const void* lds_kernel(int kind, int D, int policy);
-hipError_t launch_lds(int kind, int D, int policy, uint32_t grid,
-                      uint32_t wg_threads, size_t lds_bytes, hipStream_t st,
-                      const LdsArgs& a);
 const void* two_stream_kernel(int D, int policy);
-hipError_t launch_two_stream(int D, int policy, uint32_t grid,
-                             uint32_t wg_threads, size_t lds_bytes,
-                             hipStream_t st, const TwoStreamArgs& a);
 
 // ---- pointer chase (kernels_chase.hip)
 const void* chase_kernel(int policy);
@@ -113,8 +108,6 @@ hipError_t launch_finish_cells(const sweep_wave_rec_t* rec, const uint64_t* offs
                                uint32_t n_cells, CellRes* out, hipStream_t st);
 hipError_t launch_read_clock(uint64_t* out, hipStream_t st);
 const void* reduce_kernel(int dtype);
-hipError_t launch_reduce(int dtype, uint32_t grid, hipStream_t st,
-                         const ReduceArgs& a);
 hipError_t launch_reduce_finish(const float* partials, uint32_t n,
                                 double* out, hipStream_t st);
 

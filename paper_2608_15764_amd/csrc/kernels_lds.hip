@@ -96,29 +96,11 @@ const void* lds_kernel(int kind, int D, int policy) {
   return nullptr;
 }
 
-hipError_t launch_lds(int kind, int D, int policy, uint32_t grid,
-                      uint32_t wg_threads, size_t lds_bytes, hipStream_t st,
-                      const LdsArgs& a) {
-  const void* fn = lds_kernel(kind, D, policy);
-  if (!fn) return hipErrorInvalidValue;
-  void* args[] = {const_cast<LdsArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(grid), dim3(wg_threads), args, lds_bytes, st);
-}
-
 const void* two_stream_kernel(int D, int policy) {
   static const std::array<TwoFn, kMaxK> t[kNumPolicies] = {kTwoRow<0>, kTwoRow<1>,
                                                            kTwoRow<2>, kTwoRow<3>};
   if (D < 1 || D > kMaxK || policy < 0 || policy >= kNumPolicies) return nullptr;
   return reinterpret_cast<const void*>(t[policy][D - 1]);
-}
-
-hipError_t launch_two_stream(int D, int policy, uint32_t grid,
-                             uint32_t wg_threads, size_t lds_bytes,
-                             hipStream_t st, const TwoStreamArgs& a) {
-  const void* fn = two_stream_kernel(D, policy);
-  if (!fn) return hipErrorInvalidValue;
-  void* args[] = {const_cast<TwoStreamArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(grid), dim3(wg_threads), args, lds_bytes, st);
 }
 
 }  // namespace ilp

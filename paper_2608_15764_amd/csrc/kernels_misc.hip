@@ -284,14 +284,6 @@ const void* reduce_kernel(int dtype) {
   }
 }
 
-hipError_t launch_reduce(int dtype, uint32_t grid, hipStream_t st,
-                         const ReduceArgs& a) {
-  const void* fn = reduce_kernel(dtype);
-  if (!fn) return hipErrorInvalidValue;
-  void* args[] = {const_cast<ReduceArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, st);
-}
-
 // Final combine in FP64, in a fixed order: thread t sums partial pairs
 // t, t+256, ... and the 256 totals are added up a fixed binary tree.
 __global__ __launch_bounds__(256) void reduce_finish(const float* partials,

@@ -86,13 +86,4 @@ const void* plain_kernel(int K, int V, int policy) {
   return reinterpret_cast<const void*>(table(vi, policy)[K - 1]);
 }
 
-hipError_t launch_plain(int K, int V, int policy, uint32_t grid,
-                        size_t lds_bytes, hipStream_t st, const PlainArgs& a) {
-  const void* fn = plain_kernel(K, V, policy);
-  if (!fn) return hipErrorInvalidValue;
-  void* args[] = {const_cast<PlainArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(grid), dim3(kPlainWgThreads), args,
-                         lds_bytes, st);
-}
-
 }  // namespace ilp

@@ -207,6 +207,8 @@ int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   if (!p.fn) return fail(SWEEP_EINVAL, "no kernel for this cell");
   p.grid = p.plan.pub.grid_wgs;
   p.threads = p.plan.pub.wg_threads;
+  if (c.kind == SWEEP_KIND_PLAIN && p.threads != (uint32_t)kPlainWgThreads)
+    return fail(SWEEP_EINVAL, "plain cells run 256-thread workgroups");
   p.lds = p.plan.lds_ring_bytes;
   if (pin && p.plan.pub.lds_pad_bytes > p.lds) p.lds = p.plan.pub.lds_pad_bytes;
   const auto key = std::make_tuple(p.fn, p.threads, p.lds);
@@ -231,27 +233,31 @@ int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
   return SWEEP_OK;
 }
 
+// Launches kernel `fn` whose one parameter is the struct `a`.  With events,
+// hipExtLaunchKernel stamps them from the kernel's own dispatch (its start
+// and its end), with no marker packets between kernels; without (as under
+// graph capture), a plain launch.
+template <class Args>
+hipError_t launch_timed(const void* fn, uint32_t grid, uint32_t threads, size_t lds,
+                        hipStream_t st, const Args& a, hipEvent_t e0, hipEvent_t e1) {
+  void* args[] = {const_cast<Args*>(&a)};
+  if (e0 || e1)
+    return hipExtLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, st, e0, e1, 0);
+  return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, st);
+}
+
 // Launches the cell's kernel; the wave records go to `rec`, which holds at
-// least the cell's waves.  With events, hipExtLaunchKernel stamps them from
-// the kernel's own dispatch (its start and its end), with no marker packets
-// between kernels; without (under graph capture), a plain launch.
+// least the cell's waves.
 hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
                    uint32_t* lane_out, hipEvent_t e0, hipEvent_t e1) {
-  PlainArgs pa{};
-  LdsArgs la{};
-  void* args[1];
   if (p.c.kind == SWEEP_KIND_PLAIN) {
-    pa = PlainArgs{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-                   p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
-    args[0] = &pa;
-  } else {
-    la = LdsArgs{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-                 p.plan.stride, rec, lane_out, p.plan.wg_waves};
-    args[0] = &la;
+    const PlainArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+                      p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
+    return launch_timed(p.fn, p.grid, p.threads, p.lds, st, a, e0, e1);
   }
-  if (e0 || e1)
-    return hipExtLaunchKernel(p.fn, dim3(p.grid), dim3(p.threads), args, p.lds, st, e0, e1, 0);
-  return hipLaunchKernel(p.fn, dim3(p.grid), dim3(p.threads), args, p.lds, st);
+  const LdsArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
+                  p.plan.stride, rec, lane_out, p.plan.wg_waves};
+  return launch_timed(p.fn, p.grid, p.threads, p.lds, st, a, e0, e1);
 }
 
 // Copies the record offsets of `n` cells (n + 1 entries) to the device.
@@ -565,6 +571,7 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
   size_t lds = ring;
   if (pin_of(opt)) lds = std::max<size_t>(lds, pin_padding(1, ring, d->lds_per_cu, d->lds_per_wg_max));
   const void* fn = two_stream_kernel(depth, pol);
+  if (!fn) return fail(SWEEP_EINVAL, "no two-stream kernel for this depth and policy");
   hipFuncAttributes fa;
   HIP_TRY(hipFuncGetAttributes(&fa, fn));
   int nb = 0;
@@ -578,9 +585,7 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
   a.lane_out = opt ? opt->lane_out : nullptr;
   hipStream_t st = as_stream(opt);
   SW_TRY(upload_offsets(*d, {0ull, (uint64_t)wa, (uint64_t)wa + wb}, st));
-  HIP_TRY(hipEventRecord(d->ev[0], st));
-  HIP_TRY(launch_two_stream(depth, pol, grid, threads, lds, st, a));
-  HIP_TRY(hipEventRecord(d->ev[1], st));
+  HIP_TRY(launch_timed(fn, grid, threads, lds, st, a, d->ev[0], d->ev[1]));
   HIP_TRY(launch_finish_cells(rec, d->offs, 2, d->res, st));
   HIP_TRY(hipMemcpyAsync(d->res_h, d->res, 2 * sizeof(CellRes), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(d->ev[2], st));
@@ -854,6 +859,7 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
   if (a.n_vec - a.n_groups * 256 > (uint64_t)grid * 256)
     return fail(SWEEP_EINVAL, "grid too small for the ragged remainder");
   const void* fn = reduce_kernel(dtype);
+  if (!fn) return fail(SWEEP_EINVAL, "no reduction kernel for this dtype");
   hipFuncAttributes fa;
   HIP_TRY(hipFuncGetAttributes(&fa, fn));
   int nb = 0;
@@ -865,9 +871,7 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
   a.rec = d->rec;
   hipStream_t st = as_stream(opt);
   SW_TRY(upload_offsets(*d, {0ull, (uint64_t)grid * 4}, st));
-  HIP_TRY(hipEventRecord(d->ev[0], st));
-  HIP_TRY(launch_reduce(dtype, grid, st, a));
-  HIP_TRY(hipEventRecord(d->ev[1], st));
+  HIP_TRY(launch_timed(fn, grid, 256u, 0, st, a, d->ev[0], d->ev[1]));
   HIP_TRY(launch_reduce_finish(d->partials, grid, d->dsum, st));
   HIP_TRY(launch_finish_cells(d->rec, d->offs, 1, d->res, st));
   HIP_TRY(hipMemcpyAsync(d->dsum_h, d->dsum, sizeof(double), hipMemcpyDeviceToHost, st));
