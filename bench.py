@@ -339,7 +339,6 @@ def main():
         ks_best = sorted({m["K"] for m in meta if m["waves_per_cu"] == best_w})
         result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf)
     del buf
-    torch.cuda.empty_cache()
     if not a.no_extras:
         result["rows"] = run_extras(a, isw, sweeps)
     line = json.dumps(result, default=str)
@@ -372,7 +371,6 @@ def run_extras(a, isw, sweeps, only=None):
             pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2)
         rows["c4_wall_s"] = time.perf_counter() - t
         del buf
-        torch.cuda.empty_cache()
     if only in (None, "c5a"):
         t = time.perf_counter()
         rows["c5a_batched"] = sweeps.batched_autotuned()

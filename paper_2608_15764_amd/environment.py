@@ -4,7 +4,7 @@ The method records driver, runtime, clocks, power limit and throttle state
 for every session and checks that no throttling happened during collection
 (Section 3, "Environment").  This module collects the same facts on the
 MI355X host: runtime versions, the host CPU, and the GPU's current shader
-and memory clock levels, power, power cap, temperatures and performance
+memory, fabric and SoC clock levels, power, power cap, temperatures and performance
 level from sysfs, taken before and after a session so that a clock change
 is visible beside the numbers.  Everything is read from files; no helper
 program is started from the measuring process.
@@ -56,6 +56,8 @@ def sysfs_metrics(device_dir=None):
     m = {"device": d,
          "sclk": _current_level(_read(os.path.join(d, "pp_dpm_sclk"))),
          "mclk": _current_level(_read(os.path.join(d, "pp_dpm_mclk"))),
+         "fclk": _current_level(_read(os.path.join(d, "pp_dpm_fclk"))),
+         "socclk": _current_level(_read(os.path.join(d, "pp_dpm_socclk"))),
          "perf_level": _read(os.path.join(d, "power_dpm_force_performance_level")),
          "link": _read(os.path.join(d, "current_link_speed"))}
     hw = os.path.join(d, "hwmon")
