@@ -344,7 +344,9 @@ int sweep_autotune(const void* buf, size_t bytes,
  * TwoSum into an (s, c) pair (Sum2 of Ogita, Rump and Oishi, 2005; FP8 in
  * chunks of 64 values, whose FP32 sum is exact); pairs are merged per wave
  * and per workgroup in FP32 with TwoSum, and only the final combine of the
- * per-workgroup pairs is done in FP64.  Deterministic for a fixed grid.
+ * per-workgroup pairs is done in FP64.  Every lane keeps eight 16-byte
+ * loads in flight at waves_per_cu = 4 and four above.  Deterministic for a
+ * fixed grid and waves_per_cu.
  *   payload  device, 16-byte aligned; n_elems elements of `dtype`
  *   n_elems  any count (0 gives 0.0)
  *   dtype    SWEEP_F32, SWEEP_BF16 or SWEEP_FP8_E4M3

@@ -57,7 +57,7 @@ struct TwoStreamArgs {
 // then the ragged remainder (whole 16-byte vectors, then the last bytes).
 struct ReduceArgs {
   const uint8_t* payload;
-  uint64_t n_groups;        // full 4 KiB wave-groups
+  uint64_t n_groups;        // full wave-groups (loads x 1 KiB each)
   uint64_t n_vec;           // whole 16-byte vectors
   uint64_t n_bytes;         // payload bytes
   float* partials;          // 2 floats (s, c) per workgroup
@@ -107,7 +107,8 @@ hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,
 hipError_t launch_finish_cells(const sweep_wave_rec_t* rec, const uint64_t* offsets,
                                uint32_t n_cells, CellRes* out, hipStream_t st);
 hipError_t launch_read_clock(uint64_t* out, hipStream_t st);
-const void* reduce_kernel(int dtype);
+// `loads` (4 or 8) 16-byte loads in flight per lane per iteration.
+const void* reduce_kernel(int dtype, int loads);
 hipError_t launch_reduce_finish(const float* partials, uint32_t n,
                                 double* out, hipStream_t st);
 

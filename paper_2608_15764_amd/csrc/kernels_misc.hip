@@ -195,10 +195,11 @@ __device__ __forceinline__ float decode_one(const uint8_t* p) {
   }
 }
 
-constexpr int kRedLoads = 4;   // loads in flight per lane per iteration
-
-template <int DT>
+// NL = loads in flight per lane per iteration (4 or 8); a wave-group is
+// NL x 64 lanes x 16 bytes.
+template <int DT, int NL>
 __global__ __launch_bounds__(256) void reduce_fp(ReduceArgs a) {
+  static_assert(NL % 4 == 0, "FP8 groups of four vectors are summed exactly");
   const uint64_t t0 = wall_ticks();
   const uint32_t lane = lane_id();
   const uint32_t wv = wave_in_wg();
@@ -206,29 +207,33 @@ __global__ __launch_bounds__(256) void reduce_fp(ReduceArgs a) {
   const uint32_t n_waves = gridDim.x * 4;
   Pair p{0.0f, 0.0f};
 
-  // full wave-groups: 4 loads x 64 lanes x 16 bytes = 4 KiB
+  // full wave-groups; all NL loads are issued before any is consumed
 #pragma unroll 1
   for (uint64_t g = wid; g < a.n_groups; g += n_waves) {
-    const uint8_t* base = a.payload + g * (kRedLoads * kWave * 16);
-    u32x4 v[kRedLoads];
+    const uint8_t* base = a.payload + g * (NL * kWave * 16);
+    u32x4 v[NL];
 #pragma unroll
-    for (int j = 0; j < kRedLoads; ++j)
+    for (int j = 0; j < NL; ++j)
       v[j] = load_seg<16, SWEEP_CACHE_NT>(base + j * (kWave * 16), lane);
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (DT == SWEEP_FP8_E4M3) {
       // 64 e4m3 values are k * 2^-9 with |k| <= 64 * 229376 < 2^24, so
-      // their FP32 sum is exact; one TwoSum per 64 values
-      float t = 0.0f;
+      // their FP32 sum is exact; one TwoSum per 64 values (four vectors)
 #pragma unroll
-      for (int j = 0; j < kRedLoads; ++j) t += fp8_vec_sum(v[j]);
-      add_term(p, t);
+      for (int q = 0; q < NL / 4; ++q) {
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t += fp8_vec_sum(v[4 * q + j]);
+        add_term(p, t);
+      }
     } else {
 #pragma unroll
-      for (int j = 0; j < kRedLoads; ++j) acc_vec<DT>(p, v[j]);
+      for (int j = 0; j < NL; ++j) acc_vec<DT>(p, v[j]);
     }
   }
   // remaining whole vectors, one per thread of the grid
   const uint64_t gtid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint64_t first_rem = a.n_groups * (kRedLoads * kWave);
+  const uint64_t first_rem = a.n_groups * (NL * kWave);
   if (first_rem + gtid < a.n_vec) {
     const u32x4 v = *reinterpret_cast<const u32x4*>(a.payload + (first_rem + gtid) * 16);
     acc_vec<DT>(p, v);
@@ -275,13 +280,20 @@ __global__ __launch_bounds__(256) void reduce_fp(ReduceArgs a) {
   }
 }
 
-const void* reduce_kernel(int dtype) {
+template <int NL>
+const void* reduce_of(int dtype) {
   switch (dtype) {
-    case SWEEP_F32: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_F32>);
-    case SWEEP_BF16: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_BF16>);
-    case SWEEP_FP8_E4M3: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_FP8_E4M3>);
+    case SWEEP_F32: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_F32, NL>);
+    case SWEEP_BF16: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_BF16, NL>);
+    case SWEEP_FP8_E4M3: return reinterpret_cast<const void*>(&reduce_fp<SWEEP_FP8_E4M3, NL>);
     default: return nullptr;
   }
+}
+
+const void* reduce_kernel(int dtype, int loads) {
+  if (loads == 4) return reduce_of<4>(dtype);
+  if (loads == 8) return reduce_of<8>(dtype);
+  return nullptr;
 }
 
 // Final combine in FP64, in a fixed order: thread t sums partial pairs

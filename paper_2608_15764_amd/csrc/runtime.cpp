@@ -855,10 +855,13 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
   a.payload = static_cast<const uint8_t*>(payload);
   a.n_bytes = (uint64_t)n_elems * esz;
   a.n_vec = a.n_bytes / 16;
-  a.n_groups = a.n_vec / 256;
-  if (a.n_vec - a.n_groups * 256 > (uint64_t)grid * 256)
+  // Loads in flight per lane: 8 at one wave per SIMD, 4 above, so that at
+  // least 8 MiB is in flight at every occupancy of the default grid.
+  const int loads = waves_per_cu == 4 ? 8 : 4;
+  a.n_groups = a.n_vec / (64u * (uint64_t)loads);
+  if (a.n_vec - a.n_groups * 64u * (uint64_t)loads > (uint64_t)grid * 256)
     return fail(SWEEP_EINVAL, "grid too small for the ragged remainder");
-  const void* fn = reduce_kernel(dtype);
+  const void* fn = reduce_kernel(dtype, loads);
   if (!fn) return fail(SWEEP_EINVAL, "no reduction kernel for this dtype");
   hipFuncAttributes fa;
   HIP_TRY(hipFuncGetAttributes(&fa, fn));

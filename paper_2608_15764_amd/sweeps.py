@@ -360,7 +360,7 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
 
 
 # ----------------------------------------------- precision reduction (C5b)
-def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(8, 12, 16, 24, 32),
+def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 32),
                   seed=SEED_BASE + 5):
     """Streaming FP32 / BF16 / FP8 sums of N(0,1) payloads.  The occupancy
     is tuned per payload type (median of 3 launches per choice), then n

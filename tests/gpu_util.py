@@ -30,3 +30,17 @@ def decode_lanes(t, n_waves):
 
 def host_words(buf):
     return buf.cpu().numpy().view(np.uint32)
+
+
+def reduce_lane_terms(kind, n, waves, waves_per_cu):
+    """Upper bound on the TwoSum terms one lane of the streaming sum adds:
+    its share of the full wave-groups (8 loads per lane at 4 waves per CU,
+    4 above; FP8 adds one term per four vectors), one remainder vector and
+    the trailing elements."""
+    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
+    eb = {"f32": 4, "bf16": 2, "fp8_e4m3": 1}[kind]
+    loads = 8 if waves_per_cu == 4 else 4
+    groups = (n * eb // 16) // (64 * loads)
+    g_lane = -(-groups // waves) if waves else 0
+    per_group = loads * per_vec if kind != "fp8_e4m3" else loads // 4
+    return g_lane * per_group + per_vec + 16

@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from gpu_util import decode_recs, recs
+from gpu_util import decode_recs, recs, reduce_lane_terms
 from oracle import checksums, fpsum, plan as oplan, splitmix
 from paper_2608_15764_amd import ilpsweep as isw
 from paper_2608_15764_amd import sweeps
@@ -210,6 +210,8 @@ def test_precision_sum_full_size(kind):
     s1, r = isw.sweep_reduce_fp(p, n, dt, 32)
     s2, _ = isw.sweep_reduce_fp(p, n, dt, 32)
     assert s1 == s2                              # deterministic
+    s4, r4 = isw.sweep_reduce_fp(p, n, dt, 4)    # eight loads per lane
+    assert s4 == isw.sweep_reduce_fp(p, n, dt, 4)[0]
     host = p.cpu().numpy()
     del p
     torch.cuda.empty_cache()
@@ -226,11 +228,9 @@ def test_precision_sum_full_size(kind):
             (bits.astype(np.uint32) << np.uint32(16)).view(np.float32)
         exact = fpsum.exact_sum(vals)
         absx = float(np.abs(vals, dtype=np.float64).sum())
-    err = abs(s1 - exact)
-    print(f"{kind}: gpu {s1!r} exact {exact!r} |err| {err:.3e} "
-          f"({r['gbps']:.0f} GB/s)")
-    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
-    groups = (n * eb // 16) // 256
-    g_lane = -(-groups // r["waves"])
-    terms = g_lane * (4 * per_vec if kind != "fp8_e4m3" else 1) + per_vec + 16
-    assert err <= fpsum.sum2_bound(absx, terms, 8, r["grid_wgs"])
+    for got, res, w in ((s1, r, 32), (s4, r4, 4)):
+        err = abs(got - exact)
+        print(f"{kind} at {w} waves/CU: gpu {got!r} exact {exact!r} |err| {err:.3e} "
+              f"({res['gbps']:.0f} GB/s)")
+        terms = reduce_lane_terms(kind, n, res["waves"], w)
+        assert err <= fpsum.sum2_bound(absx, terms, 8, res["grid_wgs"])

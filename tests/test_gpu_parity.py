@@ -10,7 +10,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from gpu_util import (decode_lanes, decode_recs, dev_bytes, host_words,
-                      lanes, recs)
+                      lanes, recs, reduce_lane_terms)
 from oracle import checksums, fpsum, plan as oplan, splitmix
 from paper_2608_15764_amd import ilpsweep as isw
 import synth
@@ -226,15 +226,12 @@ def _oracle_sum(kind, payload_u8):
     return fpsum.exact_sum_e4m3(a)
 
 
-def _bound(kind, payload_u8, n, res):
+def _bound(kind, payload_u8, n, res, w):
     a = payload_u8.cpu().numpy()
     x = {"f32": lambda: fpsum.decode_f32(a.view(np.uint32)),
          "bf16": lambda: fpsum.decode_bf16(a.view(np.uint16)),
          "fp8_e4m3": lambda: fpsum.decode_e4m3(a)}[kind]()
-    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
-    groups = (n * fpsum_bytes(kind) // 16) // 256
-    g_lane = -(-groups // res["waves"]) if res["waves"] else 0
-    terms = g_lane * (4 * per_vec if kind != "fp8_e4m3" else 1) + per_vec + 16
+    terms = reduce_lane_terms(kind, n, res["waves"], w)
     return fpsum.sum2_bound(float(np.abs(x).sum()), terms, 8, res["grid_wgs"])
 
 
@@ -242,16 +239,17 @@ def fpsum_bytes(kind):
     return {"f32": 4, "bf16": 2, "fp8_e4m3": 1}[kind]
 
 
+@pytest.mark.parametrize("w", [4, 8])
 @pytest.mark.parametrize("kind", ["f32", "bf16", "fp8_e4m3"])
-@pytest.mark.parametrize("n", [0, 1, 7, 1000, 4096 * 3 + 5, (1 << 20) + 3])
-def test_reduce_matches_exact_sum(kind, n):
+@pytest.mark.parametrize("n", [0, 1, 7, 1000, 4096 * 3 + 5, 8192 * 5 + 9, (1 << 20) + 3])
+def test_reduce_matches_exact_sum(kind, n, w):
     payload = synth.normal_payload(kind, n, seed=n + 17, device="cuda")
     pad = torch.zeros(max(16, payload.numel() + 16), dtype=torch.uint8, device="cuda")
     pad[:payload.numel()] = payload
-    got, res = _gpu_sum(kind, pad, n)
+    got, res = _gpu_sum(kind, pad, n, w)
     want = _oracle_sum(kind, payload)
     err = abs(got - want)
-    assert err <= _bound(kind, payload, n, res), (got, want)
+    assert err <= _bound(kind, payload, n, res, w), (got, want)
 
 
 def _negated(u8, kind):
@@ -268,13 +266,15 @@ def test_reduce_special_cases(kind):
     dt = synth.DTYPES[kind]
     # constant payload: exact n * x
     x = torch.full((n,), 1.5, dtype=torch.float32, device="cuda").to(dt)
-    got, _ = _gpu_sum(kind, x.view(torch.uint8), n)
-    assert got == n * 1.5
+    for w in (4, 8):
+        got, _ = _gpu_sum(kind, x.view(torch.uint8), n, w)
+        assert got == n * 1.5
     # +v / -v pairs cancel exactly
     v = synth.normal_payload(kind, n, seed=3, device="cuda")
     both = torch.cat([v, _negated(v, kind)])
-    got, _ = _gpu_sum(kind, both, 2 * n)
-    assert got == 0.0
+    for w in (4, 8):
+        got, _ = _gpu_sum(kind, both, 2 * n, w)
+        assert got == 0.0
 
 
 def test_reduce_recovers_absorbed_terms():
