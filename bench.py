@@ -93,6 +93,10 @@ def parse():
                          "per call for a separate rocprofv3 counter run")
     ap.add_argument("--manifest", default=None,
                     help="launch manifest path for --only c3counters")
+    ap.add_argument("--c5b-waves", default=None,
+                    help="fixed waves per CU for the precision sums instead of "
+                         "tuning, e.g. f32=8,bf16=8,fp8_e4m3=4 (for profiling "
+                         "the tuned launches alone)")
     ap.add_argument("--json-out", default=None,
                     help="also write the full result to this file")
     ap.add_argument("--record", default=None,
@@ -377,7 +381,10 @@ def run_extras(a, isw, sweeps, only=None):
         rows["c5a_batched"]["wall_s"] = time.perf_counter() - t
     if only in (None, "c5b"):
         t = time.perf_counter()
-        rows["c5b_precision"] = sweeps.precision_sum()
+        fixed = None
+        if a.c5b_waves:
+            fixed = {k: int(v) for k, v in (kv.split("=") for kv in a.c5b_waves.split(","))}
+        rows["c5b_precision"] = sweeps.precision_sum(waves_fixed=fixed)
         rows["c5b_precision"]["wall_s"] = time.perf_counter() - t
     if only in (None, "next"):
         t = time.perf_counter()

@@ -361,10 +361,11 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
 
 # ----------------------------------------------- precision reduction (C5b)
 def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 32),
-                  seed=SEED_BASE + 5):
+                  seed=SEED_BASE + 5, waves_fixed=None):
     """Streaming FP32 / BF16 / FP8 sums of N(0,1) payloads.  The occupancy
     is tuned per payload type (median of 3 launches per choice), then n
-    launches are timed at the chosen occupancy."""
+    launches are timed at the chosen occupancy.  ``waves_fixed`` ({kind:
+    waves_per_cu}) skips the tuning for the kinds it names."""
     import synth
     out = {}
     for kind, dt in (("f32", isw.F32), ("bf16", isw.BF16), ("fp8_e4m3", isw.FP8_E4M3)):
@@ -372,12 +373,16 @@ def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 
         n_el = payload_bytes // eb
         p = synth.normal_payload(kind, n_el, seed, device="cuda")
         torch.cuda.synchronize()
-        isw.sweep_reduce_fp(p, n_el, dt, waves_choices[0])
         tune = {}
-        for w in waves_choices:
-            tune[w] = _median([isw.sweep_reduce_fp(p, n_el, dt, w)[1]["gbps"]
-                               for _ in range(3)])
-        best_w = max(tune, key=tune.get)
+        if waves_fixed and kind in waves_fixed:
+            best_w = waves_fixed[kind]
+        else:
+            isw.sweep_reduce_fp(p, n_el, dt, waves_choices[0])
+            for w in waves_choices:
+                tune[w] = _median([isw.sweep_reduce_fp(p, n_el, dt, w)[1]["gbps"]
+                                   for _ in range(3)])
+            best_w = max(tune, key=tune.get)
+        isw.sweep_reduce_fp(p, n_el, dt, best_w)    # warm-up at the chosen occupancy
         gs, sums = [], []
         for _ in range(n):
             s, r = isw.sweep_reduce_fp(p, n_el, dt, best_w)

@@ -432,6 +432,11 @@ def test_sweep_drivers_run_small():
     assert lad[8 << 10]["default"]["mean_ns"] > 0
     ps = sweeps.precision_sum(payload_bytes=1 << 20, n=2)
     assert all(v["deterministic"] for v in ps.values())
+    fixed = {"f32": 4, "bf16": 8, "fp8_e4m3": 4}
+    ps2 = sweeps.precision_sum(payload_bytes=1 << 20, n=2, waves_fixed=fixed)
+    for kind, w in fixed.items():
+        assert ps2[kind]["waves_per_cu"] == w and ps2[kind]["tuning_gbps"] == {}
+        assert ps2[kind]["sum"] == ps[kind]["sum"] or ps[kind]["waves_per_cu"] != w
     fi = sweeps.fixed_iteration_arm(buf, nbytes, Ks=(1, 2), waves_per_cu=8, n=1)
     assert fi["issued_bytes"][2] == 2 * fi["issued_bytes"][1]
     sg = sweeps.streaming_gate(buf, nbytes, launches=3)
