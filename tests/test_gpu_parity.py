@@ -505,3 +505,53 @@ def test_persistent_graph_rejects_bad_cells():
     with pytest.raises(isw.SweepError):
         isw.sweep_graph_create([])
     assert isw.lib.sweep_graph_destroy(None) == isw.OK
+
+
+def test_concurrent_callers_get_their_own_results():
+    """Calls from several host threads (ctypes releases the GIL) are
+    serialised by the library; every caller gets the sinks of its own
+    buffer, and errors stay with the thread that caused them."""
+    import threading
+    nbytes = 4 << 20
+    bufs = [dev_bytes(nbytes) for _ in range(3)]
+    for i, b in enumerate(bufs):
+        isw.sweep_fill_u32(b, nbytes, SEED + 40 + i)
+    torch.cuda.synchronize()
+    want = [checksums.whole_buffer(splitmix.buffer_words(SEED + 40 + i, nbytes))
+            for i in range(3)]
+    g = isw.sweep_graph_create([isw.make_cell(bufs[2], nbytes, 2, 16, 8, nbytes // 16)])
+    got, errs = {}, {}
+
+    def plain(i):
+        for rep in range(20):
+            r = isw.sweep_plain(bufs[i], nbytes, 1 + rep % 4, 16, 8, nbytes // 16)
+            got.setdefault(i, set()).add((r["sum32"], r["xor32"]))
+        errs[i] = isw.lib.sweep_last_error()     # this thread never failed
+
+    def graph():
+        for _ in range(20):
+            res, _ = isw.sweep_graph_launch(g)
+            got.setdefault(2, set()).add((res[0]["sum32"], res[0]["xor32"]))
+
+    def failing():
+        for _ in range(20):
+            try:
+                isw.sweep_plain(bufs[0], nbytes, 17, 16, 8, nbytes // 16)
+            except isw.SweepError as e:
+                errs.setdefault("codes", set()).add(e.code)
+        errs["msg"] = isw.lib.sweep_last_error()
+
+    ts = [threading.Thread(target=plain, args=(0,)), threading.Thread(target=plain, args=(1,)),
+          threading.Thread(target=graph), threading.Thread(target=failing)]
+    try:
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join(timeout=120)
+        assert not any(t.is_alive() for t in ts)
+    finally:
+        isw.sweep_graph_destroy(g)
+    for i in range(3):
+        assert got[i] == {want[i]}, i
+    assert errs["codes"] == {isw.EINVAL} and errs["msg"]
+    assert errs[0] == b"" and errs[1] == b""
