@@ -524,7 +524,8 @@ def test_concurrent_callers_get_their_own_results():
 
     def plain(i):
         for rep in range(20):
-            r = isw.sweep_plain(bufs[i], nbytes, 1 + rep % 4, 16, 8, nbytes // 16)
+            K = (1, 2, 4, 8)[rep % 4]             # whole passes: every K divides
+            r = isw.sweep_plain(bufs[i], nbytes, K, 16, 8, nbytes // 16)
             got.setdefault(i, set()).add((r["sum32"], r["xor32"]))
         errs[i] = isw.lib.sweep_last_error()     # this thread never failed
 
