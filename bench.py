@@ -87,7 +87,7 @@ def parse():
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
                     choices=["c3", "c4", "c5a", "c5b", "c3counters", "c2counters",
-                             "next"],
+                             "c4counters", "next"],
                     help="run only one extra configuration (no K sweep); "
                          "c3counters runs the allocation-sweep cells one launch "
                          "per call for a separate rocprofv3 counter run")
@@ -194,6 +194,10 @@ def main():
         GIB = 1 << 30
         sizes = [512 << 20, GIB, 2 * GIB, 4 * GIB, 8 * GIB, 20 * GIB]
         man = sweeps.allocation_counter_pass(sizes, policy=policy, manifest=a.manifest)
+        print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only == "c4counters":
+        man = sweeps.lds_counter_pass(manifest=a.manifest)
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c2counters":

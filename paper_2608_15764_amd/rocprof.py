@@ -199,7 +199,7 @@ def attribute(rows, manifest, kernel_substr="plain_kload"):
     return out
 
 
-CELL_KEYS = ("bytes", "waves_per_cu", "K", "order")
+CELL_KEYS = ("path", "bytes", "waves_per_cu", "K", "order")
 
 
 def cell_key(m):
@@ -207,12 +207,12 @@ def cell_key(m):
     return tuple(m[k] for k in CELL_KEYS if k in m)
 
 
-def cell_table(runs, manifest, fetch_scale=None):
+def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload"):
     """Per cell: median of every counter over the non-warm-up launches, plus
     the derived L2 hit rate and scaled bytes."""
     cells = {}
     for rows in runs:
-        for c, pairs in attribute(rows, manifest).items():
+        for c, pairs in attribute(rows, manifest, kernel_substr).items():
             for m, v in pairs:
                 if m["warmup"] or v is None:
                     continue
@@ -252,6 +252,8 @@ def main(argv=None):
     c3.add_argument("--counters", nargs="+", required=True,
                     help="counter_collection CSVs (or directories), one per pass")
     c3.add_argument("--fetch-scale", type=float, default=None)
+    c3.add_argument("--kernel", default="plain_kload",
+                    help="substring naming the manifest's kernels")
     c3.add_argument("--command", action="append", default=[])
     c3.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -259,7 +261,8 @@ def main(argv=None):
         import json
         with open(a.manifest) as f:
             man = json.load(f)
-        tab = cell_table([counter_rows(p) for p in a.counters], man, a.fetch_scale)
+        tab = cell_table([counter_rows(p) for p in a.counters], man, a.fetch_scale,
+                         a.kernel)
         lines = ["# rocprofv3 per-cell counters (generated by paper_2608_15764_amd.rocprof)"]
         lines += [f"# command: {c}" for c in a.command]
         keys = [k for k in CELL_KEYS if man and k in man[0]]

@@ -427,6 +427,10 @@ def test_sweep_drivers_run_small():
     assert all(v["checksums_consistent"] for v in al.values())
     of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
     assert set(of[1 << 20]) == {"round_robin", "blocked"}
+    man = sweeps.lds_counter_pass(nbytes=4 << 20, waves_list=(1,), depths=(2, 5), L=1 << 18,
+                                  reps=2)
+    assert len(man) == 8 and {m["path"] for m in man} == {"lds_async", "lds_matched"}
+    assert all(m["issued_bytes"] > 0 and m["gbps"] > 0 for m in man)
     lad = sweeps.latency_ladder(footprints=[8 << 10, 1 << 20], hops=256, n_samples=128,
                                 evict_bytes=16 << 20)
     assert lad[8 << 10]["default"]["mean_ns"] > 0

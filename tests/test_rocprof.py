@@ -93,3 +93,25 @@ def test_cell_table_keys_on_occupancy(tmp_path):
     row = tab[(1 << 30, 4, 4, "asc")]
     assert row["TCC_HIT_sum"] == 41.5                 # warm-up (40) excluded
     assert row["l2_hit_rate"] == pytest.approx(41.5 / 131.5)
+
+
+def test_cell_table_keys_on_path_and_kernel(tmp_path):
+    """LDS-path manifests carry a path field and name other kernels."""
+    KA = "void ilp::lds_kernel_t<1, 4, 0>(ilp::LdsArgs)"
+    KM = "void ilp::lds_kernel_t<2, 4, 0>(ilp::LdsArgs)"
+    man, rows = [], []
+    for path, k in (("lds_async", KA), ("lds_matched", KM)):
+        for rep in range(3):
+            man.append({"path": path, "bytes": 1 << 31, "waves_per_cu": 1, "K": 4,
+                        "order": "asc", "rep": rep, "warmup": rep == 0})
+            rows.append((k, "SQ_LDS_BANK_CONFLICT", 5.0 if path == "lds_async" else 7.0))
+    rows.insert(1, ("void ilp::plain_kload<4, 16, 3>(ilp::PlainArgs)",
+                    "SQ_LDS_BANK_CONFLICT", 99.0))        # not in the manifest
+    p = tmp_path / "l_counter_collection.csv"
+    _write_cc(p, rows)
+    tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man,
+                             kernel_substr="lds_kernel_t")
+    assert tab[("lds_async", 1 << 31, 1, 4, "asc")]["SQ_LDS_BANK_CONFLICT"] == 5.0
+    assert tab[("lds_matched", 1 << 31, 1, 4, "asc")]["SQ_LDS_BANK_CONFLICT"] == 7.0
+    with pytest.raises(ValueError):        # plain dispatches do not match it
+        rocprof.cell_table([rocprof.counter_rows(str(p))], man)
