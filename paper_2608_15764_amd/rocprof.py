@@ -207,9 +207,12 @@ def cell_key(m):
     return tuple(m[k] for k in CELL_KEYS if k in m)
 
 
-def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload"):
+def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload",
+               cus=None, xccs=None):
     """Per cell: median of every counter over the non-warm-up launches, plus
-    the derived L2 hit rate and scaled bytes."""
+    the derived L2 hit rate, scaled bytes and, given the device's CU and XCC
+    counts, the fraction of CU cycles the LDS was busy (SQ_LDS_IDX_ACTIVE is
+    summed over every CU; GRBM_GUI_ACTIVE over every XCC)."""
     cells = {}
     for rows in runs:
         for c, pairs in attribute(rows, manifest, kernel_substr).items():
@@ -227,6 +230,9 @@ def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload"):
             row["l2_hit_rate"] = hit / (hit + miss)
         if fetch_scale and "FETCH_SIZE" in row:
             row["fetch_bytes"] = row["FETCH_SIZE"] * 1024.0 * fetch_scale
+        gui = row.get("GRBM_GUI_ACTIVE")
+        if cus and xccs and gui and "SQ_LDS_IDX_ACTIVE" in row:
+            row["lds_busy_frac"] = row["SQ_LDS_IDX_ACTIVE"] / (gui / xccs * cus)
         table[key] = row
     return table
 
@@ -254,6 +260,8 @@ def main(argv=None):
     c3.add_argument("--fetch-scale", type=float, default=None)
     c3.add_argument("--kernel", default="plain_kload",
                     help="substring naming the manifest's kernels")
+    c3.add_argument("--cus", type=int, default=None)
+    c3.add_argument("--xccs", type=int, default=None)
     c3.add_argument("--command", action="append", default=[])
     c3.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -262,7 +270,7 @@ def main(argv=None):
         with open(a.manifest) as f:
             man = json.load(f)
         tab = cell_table([counter_rows(p) for p in a.counters], man, a.fetch_scale,
-                         a.kernel)
+                         a.kernel, a.cus, a.xccs)
         lines = ["# rocprofv3 per-cell counters (generated by paper_2608_15764_amd.rocprof)"]
         lines += [f"# command: {c}" for c in a.command]
         keys = [k for k in CELL_KEYS if man and k in man[0]]

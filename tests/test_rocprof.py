@@ -115,3 +115,18 @@ def test_cell_table_keys_on_path_and_kernel(tmp_path):
     assert tab[("lds_matched", 1 << 31, 1, 4, "asc")]["SQ_LDS_BANK_CONFLICT"] == 7.0
     with pytest.raises(ValueError):        # plain dispatches do not match it
         rocprof.cell_table([rocprof.counter_rows(str(p))], man)
+
+
+def test_lds_busy_fraction(tmp_path):
+    K = "void ilp::lds_kernel_t<1, 8, 0>(ilp::LdsArgs)"
+    man = [{"path": "lds_async", "bytes": 1, "waves_per_cu": 4, "K": 8, "order": "asc",
+            "rep": r, "warmup": r == 0} for r in range(2)]
+    rows = []
+    for r in range(2):
+        rows += [(K, "SQ_LDS_IDX_ACTIVE", 8.0e6), (K, "GRBM_GUI_ACTIVE", 8.0e6)]
+    p = tmp_path / "b_counter_collection.csv"
+    _write_cc(p, rows)
+    tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man, kernel_substr="lds_kernel_t",
+                             cus=256, xccs=8)
+    # 8e6 busy CU-cycles over 1e6 cycles x 256 CUs
+    assert tab[("lds_async", 1, 4, 8, "asc")]["lds_busy_frac"] == pytest.approx(8e6 / 256e6)
