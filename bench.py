@@ -377,6 +377,11 @@ def run_extras(a, isw, sweeps, only=None):
         rows["c4_two_stream_grid"] = sweeps.two_stream(
             buf, nbytes, L, depths=(4,),
             pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2)
+        # the section's own measurement: plain loads in both streams
+        rows["c4_two_stream_same_mechanism_grid"] = sweeps.two_stream(
+            buf, nbytes, L, depths=(4,),
+            pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2,
+            kind_b=isw.KIND_PLAIN)
         rows["c4_wall_s"] = time.perf_counter() - t
         del buf
     if only in (None, "c5a"):

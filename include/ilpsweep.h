@@ -276,11 +276,24 @@ int sweep_lds_matched_plain(const void* buf, size_t bytes, int depth,
  * total_logical_loads is split evenly between the streams.  out[0] is
  * stream A, out[1] stream B (each with its own sinks and window).
  *   depth 1..16; waves_plain, waves_async 0..8, not both 0.
+ * This is the cross-mechanism mix; sweep_two_stream_kind with kind_b =
+ * SWEEP_KIND_PLAIN gives the same-mechanism one the section measures.
  * Errors as sweep_plain. */
 int sweep_two_stream(const void* buf, size_t bytes, int depth,
                      int waves_plain, int waves_async,
                      uint64_t total_logical_loads, const sweep_opts_t* opt,
                      sweep_result_t out[2]);
+
+/* The same two co-resident streams with stream B's mechanism chosen:
+ * kind_b = SWEEP_KIND_LDS_ASYNC is sweep_two_stream; kind_b =
+ * SWEEP_KIND_PLAIN runs the plain K-load loop in both streams (plain loads
+ * beside plain loads in one workgroup, Section 4.4).  Stream B's sinks do
+ * not depend on kind_b: both mechanisms read the same address map.
+ *   waves_a, waves_b 0..8, not both 0; other arguments and errors as
+ *   sweep_two_stream; SWEEP_EINVAL for any other kind_b. */
+int sweep_two_stream_kind(const void* buf, size_t bytes, int depth, int waves_a,
+                          int waves_b, int kind_b, uint64_t total_logical_loads,
+                          const sweep_opts_t* opt, sweep_result_t out[2]);
 
 /* Sweep driver: runs `n` cells back to back on opt->stream in the given
  * order (ascending or reversed sweeps are the caller's ordering, Section

@@ -51,6 +51,7 @@ struct TwoStreamArgs {
   sweep_wave_rec_t* rec;   // n_waves_a + n_waves_b records
   uint32_t* lane_out;      // lanes of A then lanes of B, or null
   uint32_t waves_a, waves_b;  // per workgroup
+  uint32_t b_plain;           // 1: stream B runs the plain loop as well
 };
 
 // Precision variant: full wave-groups of 4 loads x 64 lanes x 16 bytes,

@@ -7,7 +7,8 @@
 //               ds_write_b128 and ds_read_b128), the matched plain kernel;
 //  two_stream   one workgroup per CU whose first waves run the plain
 //               batched K-load loop over the first half of the buffer and
-//               whose last waves run the LDS-direct ring over the second.
+//               whose last waves run either the LDS-direct ring or the
+//               same plain loop over the second.
 // Each wave owns `depth` 1 KiB slots of the workgroup's dynamic LDS.
 #include <array>
 #include <utility>
@@ -54,9 +55,14 @@ __global__ __launch_bounds__(1024) void two_stream_t(TwoStreamArgs a) {
   } else {
     const uint32_t wb = wv - a.waves_a;
     const uint32_t wid = blockIdx.x * a.waves_b + wb;
-    u32x4* ring = lds_ring + wb * (D * kWave);
-    async_ring_loop<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid,
-                            gridDim.x * a.waves_b, lane, ring, s, x);
+    if (a.b_plain) {
+      plain_loop16<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid,
+                           gridDim.x * a.waves_b, lane, s, x);
+    } else {
+      u32x4* ring = lds_ring + wb * (D * kWave);
+      async_ring_loop<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid,
+                              gridDim.x * a.waves_b, lane, ring, s, x);
+    }
     const uint64_t t1 = wall_ticks();
     const uint32_t base = gridDim.x * a.waves_a;
     wave_epilogue(s, x, t0, t1, base + wid, a.rec, a.lane_out);

@@ -535,7 +535,17 @@ int sweep_lds_matched_plain(const void* buf, size_t bytes, int depth,
 int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
                      int waves_async, uint64_t total_logical_loads,
                      const sweep_opts_t* opt, sweep_result_t out[2]) {
+  return sweep_two_stream_kind(buf, bytes, depth, waves_plain, waves_async,
+                               SWEEP_KIND_LDS_ASYNC, total_logical_loads, opt, out);
+}
+
+int sweep_two_stream_kind(const void* buf, size_t bytes, int depth, int waves_plain,
+                          int waves_async, int kind_b, uint64_t total_logical_loads,
+                          const sweep_opts_t* opt, sweep_result_t out[2]) {
   if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
+  if (kind_b != SWEEP_KIND_PLAIN && kind_b != SWEEP_KIND_LDS_ASYNC)
+    return fail(SWEEP_EINVAL, "stream B runs plain loads or the LDS-direct ring");
+  const bool b_plain = kind_b == SWEEP_KIND_PLAIN;
   if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
   if (depth < 1 || depth > 16) return fail(SWEEP_EINVAL, "depth must be in 1..16");
   if (waves_plain < 0 || waves_plain > 8 || waves_async < 0 || waves_async > 8 ||
@@ -561,12 +571,13 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
   a.n_vec_b = n_vec - half;
   a.waves_a = (uint32_t)waves_plain;
   a.waves_b = (uint32_t)waves_async;
+  a.b_plain = b_plain ? 1u : 0u;
   if (waves_plain) region_plan(a.n_vec_a, depth, La, grid * a.waves_a, &a.Q_a, &a.stride_a);
   if (waves_async) region_plan(a.n_vec_b, depth, Lb, grid * a.waves_b, &a.Q_b, &a.stride_b);
   if ((waves_plain && a.Q_a == 0) || (waves_async && a.Q_b == 0))
     return fail(SWEEP_EINVAL, "L is smaller than one wave-group per stream");
   const uint32_t threads = (uint32_t)(waves_plain + waves_async) * 64u;
-  const uint32_t ring = (uint32_t)waves_async * (uint32_t)depth * 1024u;
+  const uint32_t ring = b_plain ? 0u : (uint32_t)waves_async * (uint32_t)depth * 1024u;
   if (ring > d->lds_per_wg_max) return fail(SWEEP_EOCCUPANCY, "LDS ring exceeds the per-workgroup LDS");
   size_t lds = ring;
   if (pin_of(opt)) lds = std::max<size_t>(lds, pin_padding(1, ring, d->lds_per_cu, d->lds_per_wg_max));
@@ -595,7 +606,7 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
   for (int s = 0; s < 2; ++s) {
     const bool on = s == 0 ? waves_plain > 0 : waves_async > 0;
     Prepared p;
-    p.c = cell_from(s == 0 ? SWEEP_KIND_PLAIN : SWEEP_KIND_LDS_ASYNC, buf, bytes,
+    p.c = cell_from(s == 0 ? SWEEP_KIND_PLAIN : kind_b, buf, bytes,
                     depth, 16, s == 0 ? waves_plain : waves_async,
                     s == 0 ? La : Lb, opt);
     p.grid = grid;

@@ -209,22 +209,29 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
 
 
 def two_stream(buf, nbytes, L, depths=(4, 8), pairs=((4, 4),), n=3,
-               policy=isw.CACHE_DEFAULT):
+               policy=isw.CACHE_DEFAULT, kind_b=isw.KIND_LDS_ASYNC):
     """Displacement of each stream by the other (Section 4.4): for every
-    depth and (plain waves, LDS-direct waves) pair per workgroup, the
-    co-resident bandwidth of each stream against the same stream solo."""
+    depth and (stream-A waves, stream-B waves) pair per workgroup, the
+    co-resident bandwidth of each stream against the same stream solo.
+    Stream A runs plain loads; stream B the LDS-direct ring (``kind_b =
+    KIND_LDS_ASYNC``, cross-mechanism) or plain loads too (``KIND_PLAIN``,
+    the section's same-mechanism measurement)."""
     opts = isw.make_opts(cache_policy=policy)
     out = {}
+
+    def run(D, wa, wb):
+        return isw.sweep_two_stream_kind(buf, nbytes, D, wa, wb, kind_b, L, opts)
+
     for D in depths:
         for wa, wb in pairs:
             res = {"co": [], "solo_a": [], "solo_b": []}
-            isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+            run(D, wa, wb)
             for _ in range(n):
-                a, b = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+                a, b = run(D, wa, wb)
                 res["co"].append((a["gbps"], b["gbps"]))
-                a, _ = isw.sweep_two_stream(buf, nbytes, D, wa, 0, L, opts)
+                a, _ = run(D, wa, 0)
                 res["solo_a"].append(a["gbps"])
-                _, b = isw.sweep_two_stream(buf, nbytes, D, 0, wb, L, opts)
+                _, b = run(D, 0, wb)
                 res["solo_b"].append(b["gbps"])
             co_a = _median([x[0] for x in res["co"]])
             co_b = _median([x[1] for x in res["co"]])

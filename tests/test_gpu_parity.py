@@ -157,9 +157,10 @@ def test_lds_paths_match_oracle(kind, D, W, grid, n_vec, L, policy):
     assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
 
 
+@pytest.mark.parametrize("kind_b", ["lds_async", "plain"])
 @pytest.mark.parametrize("D,wa,wb", [(4, 4, 4), (8, 4, 4), (3, 1, 3),
                                      (5, 2, 0), (2, 0, 2), (16, 8, 8)])
-def test_two_stream_matches_oracle(D, wa, wb):
+def test_two_stream_matches_oracle(D, wa, wb, kind_b):
     grid = 3
     n_vec = 64 * 128
     nbytes = n_vec * 16
@@ -169,7 +170,8 @@ def test_two_stream_matches_oracle(D, wa, wb):
     ro = recs(na + nb)
     lo = lanes((na + nb) * 64)
     opts = isw.make_opts(grid_wgs=grid, wave_out=ro, lane_out=lo)
-    ra, rb = isw.sweep_two_stream(buf, nbytes, D, wa, wb, L, opts)
+    kb = isw.KIND_LDS_ASYNC if kind_b == "lds_async" else isw.KIND_PLAIN
+    ra, rb = isw.sweep_two_stream_kind(buf, nbytes, D, wa, wb, kb, L, opts)
     words = host_words(buf)
     (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
     rr = decode_recs(ro)
@@ -312,6 +314,9 @@ def test_host_validation_errors():
         isw.sweep_two_stream(buf, 1 << 20, 4, 0, 0, 1000)
     assert e.value.code == isw.EINVAL
     with pytest.raises(isw.SweepError) as e:
+        isw.sweep_two_stream_kind(buf, 1 << 20, 4, 2, 2, isw.KIND_LDS_MATCHED, 1 << 16)
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
         isw.sweep_reduce_fp(buf, 10, 9)
     assert e.value.code == isw.EINVAL
     with pytest.raises(isw.SweepError) as e:
@@ -423,6 +428,9 @@ def test_sweep_drivers_run_small():
     assert pc["checksums_equal_across_paths"] and pc[4][4]["ratio"] > 0
     ts = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((4, 4), (1, 2)), n=1)
     assert set(ts) == {"D4_A4_B4", "D4_A1_B2"}
+    tp = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((2, 2),), n=1,
+                           kind_b=isw.KIND_PLAIN)
+    assert tp["D4_A2_B2"]["co_b_gbps"] > 0
     al = sweeps.allocation_sweep([1 << 20, 4 << 20], Ks=(1, 2), waves_list=(8,), L=1 << 20, n=1)
     assert all(v["checksums_consistent"] for v in al.values())
     of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
