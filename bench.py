@@ -5,22 +5,27 @@ One step is one pass of the fixed-work plain-load K sweep: a 1 GiB seeded
 u32 buffer, 16-byte loads, K = 1..16, 2**26 logical loads per cell, at
 1..8 waves per SIMD (4..32 waves per CU), each occupancy swept in ascending
 and then reversed K order (Section 3, "Fixed-work control"; Section 4.2).
+The sweep is captured once into a hipGraph; a step is one replay of it.
 The buffer is resident in HBM before timing starts.  W untimed warm-up
-passes are followed by exactly K timed passes between two device
-synchronisations; the value is the issued bytes of the timed passes over
+steps are followed by exactly K timed steps between two device
+synchronisations; the value is the issued bytes of the timed steps over
 their wall time.
 
-After the timed region (untimed, reported beside it):
+Reported beside it:
   roofline      the plain-load kernel's algorithmic bytes per launch over
-                its mean hipEvent duration, against 8 TB/s, plus the HBM
-                traffic measured by rocprofv3 counters when the committed
-                summary matches the current kernel source
+                its mean duration (hipEvent time of the timed replays over
+                the kernels they ran), against 8 TB/s, plus the HBM traffic
+                measured by rocprofv3 counters when the committed summary
+                matches the current kernel source
+  eager_sweep   the same sweep launched cell by cell, with every kernel's
+                own dispatch-stamped event time
   cpu_baseline  the CPU oracle computing the per-wave checksums of one
-                full 1 GiB cell of the sweep (bounded sample), checked
-                against the GPU's records of the same cell
+                occupancy's whole K curve (16 full 1 GiB cells; bounded
+                sample), checked against the GPU's records of those cells
   rows          the other configurations: allocation sweep, LDS-direct vs
-                matched paths, two-stream displacement, autotuned
-                graph-batched sweep, precision sums (--no-extras skips)
+                matched paths, two-stream displacement (both mechanisms),
+                autotuned graph-batched sweep, precision sums, latency
+                ladder, order/footprint and regime map (--no-extras skips)
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build measures one
 GPU.
