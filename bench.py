@@ -299,6 +299,7 @@ def main():
         "kset_mismatch": summ["kset_mismatch"],
         "checksums_consistent": summ["checksums_consistent"],
         "residency_flags": summ["residency_flags"],
+        "anomalous_launches": summ["anomalous_launches"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),

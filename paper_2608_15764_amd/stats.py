@@ -17,7 +17,11 @@ reporting rules this module implements:
   else "rising-censored" if the peak is among the last three cells, else
   "peak-decline";
 * a residency screen flags HBM-targeted cells whose attained bandwidth
-  exceeds the HBM datasheet figure (Section 3).
+  exceeds the HBM datasheet figure (Section 3);
+* anomalous launches are disclosed rather than dropped (Section 4.2 and
+  Limitations report two slow primary launches and keep medians).  The
+  paper gives no threshold; the reading used here: a launch more than 10 %
+  below its cell's median.
 
 Little's law (Section 1, Section 2): offered bytes in flight equal
 bandwidth times latency, so in-flight bytes / bandwidth is the implied
@@ -104,6 +108,17 @@ def implied_latency_ns(in_flight, gbps):
     return in_flight / gbps
 
 
+def anomalous_launches(samples, frac=0.9):
+    """Launches below frac x their cell's median: [(K, GB/s, ratio)]."""
+    out = []
+    for k, v in sorted(samples.items()):
+        if not v:
+            continue
+        m = median(v)
+        out += [(k, x, x / m) for x in v if m > 0 and x < frac * m]
+    return out
+
+
 def summarize_curve(samples):
     """Summary of one response curve {K: [GB/s per launch]}."""
     med = per_k_medians(samples)
@@ -114,6 +129,8 @@ def summarize_curve(samples):
         "peak_K": peak_k(med),
         "knee_K": knee(med),
         "regime": classify(med) if len(med) >= 3 else None,
+        "launches": sum(len(v) for v in samples.values()),
+        "anomalous": [(int(k), x, r) for k, x, r in anomalous_launches(samples)],
     }
     if 2 in med and 8 in med:
         out["decline_2_8"] = decline(med[2], med[8])

@@ -132,6 +132,14 @@ def summarize_k_sweep(meta, runs, vec_width=16):
         out["curves"][w] = summ
     issued = [r["issued_loads"] for r in runs[0]]
     out["kset_mismatch"] = stats.kset_mismatch(issued) if issued else None
+    anom = [(w, k, x, r) for w, c in out["curves"].items() for k, x, r in c["anomalous"]]
+    out["anomalous_launches"] = {
+        "rule": "launch < 0.9 x its cell's median",
+        "count": len(anom),
+        "launches": sum(c["launches"] for c in out["curves"].values()),
+        "worst": (None if not anom else
+                  dict(zip(("waves_per_cu", "K", "gbps", "ratio"),
+                           min(anom, key=lambda a: a[3]))))}
     out["residency_flags"] = sum(
         stats.residency_flag(r["gbps"], r["issued_bytes"]) for res in runs for r in res)
     best_w = max(out["curves"], key=lambda w: max(out["curves"][w]["median_gbps"].values()))

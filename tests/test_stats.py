@@ -94,3 +94,15 @@ def test_summary_curve():
     assert out["peak_K"] == 2
     assert out["decline_2_8"] == pytest.approx((2.05 - 3.1) / 3.1)
     assert len(out["paired_declines_2_8"]) == 2
+
+
+def test_anomalous_launches_are_disclosed():
+    # ten launches per cell, one at half speed and one 8 % slow (the shape of
+    # the two disclosed primary launches); only the first crosses the 10 % rule
+    s = {2: [100.0] * 8 + [50.0, 92.0], 8: [80.0] * 10}
+    a = stats.anomalous_launches(s)
+    assert a == [(2, 50.0, 0.5)]
+    c = stats.summarize_curve(s)
+    assert c["launches"] == 20 and c["anomalous"] == [(2, 50.0, 0.5)]
+    assert c["median_gbps"][2] == 100.0            # medians are insensitive
+    assert stats.anomalous_launches({4: [10.0, 10.0, 8.0]}, frac=0.85) == [(4, 8.0, 0.8)]

@@ -45,3 +45,18 @@ def test_summarize_k_sweep_on_synthetic_results():
     assert abs(c["decline_2_8"] - (7050.5 - 7000.5) / 7000.5) < 1e-12
     assert s["kset_mismatch"] == 0.0 and s["residency_flags"] == 0
     assert c["in_flight_bytes"][2] == 4096 * 64 * 2 * 16
+    assert s["anomalous_launches"]["count"] == 0
+    assert s["anomalous_launches"]["launches"] == 16 and s["anomalous_launches"]["worst"] is None
+
+
+def test_summarize_k_sweep_discloses_a_slow_launch():
+    meta = [{"waves_per_cu": 8, "order": "asc", "K": K} for K in (1, 2, 4)]
+    runs = []
+    for p in range(5):
+        runs.append([{"gbps": (3000.0 if (p == 3 and m["K"] == 2) else 6000.0),
+                      "issued_loads": 1, "issued_bytes": 1 << 30, "sum32": 0, "xor32": 0,
+                      "waves": 2048} for m in meta])
+    s = sweeps.summarize_k_sweep(meta, runs)
+    a = s["anomalous_launches"]
+    assert a["count"] == 1 and a["launches"] == 15
+    assert a["worst"] == {"waves_per_cu": 8, "K": 2, "gbps": 3000.0, "ratio": 0.5}
