@@ -257,7 +257,7 @@ def main():
     w4 = summ["curves"].get(16)
 
     result = {
-        "metric": "attained HBM GB/s vs offered loads/thread K; % of HBM peak; K=2->8 decline %",
+        "metric": "attained HBM GB/s vs offered loads/thread K; % of HBM peak; K=2\u21928 decline %",
         "value": round(value, 1),
         "unit": "GB/s",
         "n_gpus": 1,
