@@ -162,24 +162,39 @@ def plain_k_sweep(buf, nbytes, L, policy, waves_list, Ks, passes=3, warmup=1):
 # -------------------------------------------------- allocation sweep (C3)
 def allocation_sweep(sizes, Ks=(1, 2, 4, 8), waves_list=(16,), L=1 << 30,
                      policy=isw.CACHE_BYPASS_L1, n=3, seed=SEED_BASE + 2):
-    """Fixed-work K sweep over prefixes of one buffer of the largest size."""
+    """Fixed-work K sweep over prefixes of one buffer of the largest size.
+    The whole allocation x occupancy x K sweep is captured into one hipGraph;
+    one untimed replay, then ``n`` replays whose per-cell clock windows are
+    summarised."""
     top = max(sizes)
     buf = device_buffer(top, seed)
+    cells, meta = [], []
+    for size in sizes:
+        c, m = plain_k_cells(buf, size, L, policy, waves_list, Ks)
+        c, m, _ = drop_infeasible(c, m)
+        cells += c
+        meta += [dict(x, bytes=size) for x in m]
+    g = isw.sweep_graph_create(cells)
+    try:
+        isw.sweep_graph_launch(g)                  # warm-up replay, excluded
+        runs = [isw.sweep_graph_launch(g)[0] for _ in range(n)]
+    finally:
+        isw.sweep_graph_destroy(g)
     out = {}
     for size in sizes:
-        cells, meta = plain_k_cells(buf, size, L, policy, waves_list, Ks)
-        cells, meta, dropped = drop_infeasible(cells, meta)
-        isw.sweep_run(cells)                       # warm-up pass, excluded
-        runs = [isw.sweep_run(cells) for _ in range(n)]
-        summ = summarize_k_sweep(meta, runs)
+        idx = [i for i, m in enumerate(meta) if m["bytes"] == size]
+        s_meta = [meta[i] for i in idx]
+        s_runs = [[run[i] for i in idx] for run in runs]
+        summ = summarize_k_sweep(s_meta, s_runs)
         out[size] = {
-            "issued_bytes": runs[0][0]["issued_bytes"],
-            "volume_to_allocation": runs[0][0]["issued_bytes"] / size,
+            "issued_bytes": s_runs[0][0]["issued_bytes"],
+            "volume_to_allocation": s_runs[0][0]["issued_bytes"] / size,
             "curves": {w: {"median_gbps": c["median_gbps"],
                            "decline_2_8": c.get("decline_2_8"),
                            "by_order": c["by_order"]}
                        for w, c in summ["curves"].items()},
             "checksums_consistent": summ["checksums_consistent"],
+            "anomalous_launches": summ["anomalous_launches"]["count"],
         }
     del buf
     return out
