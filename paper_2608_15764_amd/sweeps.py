@@ -353,14 +353,19 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
                                    cache_policy=t["cache_policy"]))
         V0, K0, w0, p0 = default
         plain.append(isw.make_cell(base + o, s, K0, V0, w0, s // V0, cache_policy=p0))
-    isw.sweep_batched(tuned)
-    isw.sweep_run(plain)
+    # the tuned points are captured once and replayed
+    graph = isw.sweep_graph_create(tuned)
     g_runs, g_ms, p_runs = [], [], []
-    for _ in range(n):
-        r, ms = isw.sweep_batched(tuned)
-        g_runs.append(r)
-        g_ms.append(ms)
-        p_runs.append(isw.sweep_run(plain))
+    try:
+        isw.sweep_graph_launch(graph)
+        isw.sweep_run(plain)
+        for _ in range(n):
+            r, ms = isw.sweep_graph_launch(graph)
+            g_runs.append(r)
+            g_ms.append(ms)
+            p_runs.append(isw.sweep_run(plain))
+    finally:
+        isw.sweep_graph_destroy(graph)
     sums_ok = all((a["sum32"], a["xor32"]) == (b["sum32"], b["xor32"])
                   for a, b in zip(g_runs[0], p_runs[0]))
     pts = []
