@@ -1,9 +1,10 @@
 """Sweep drivers: the experiment designs of the method on top of the C ABI.
 
 Each driver builds cells, runs them through the native sweep driver
-(``sweep_run``: back-to-back launches, per-cell events and clock windows,
-one synchronisation) or the graph-batched path (``sweep_batched``), and
-summarises the launches with :mod:`stats`.
+(``sweep_run``: back-to-back launches, per-cell dispatch-stamped events and
+clock windows, one synchronisation) or a captured graph
+(``sweep_graph_create`` once, ``sweep_graph_launch`` per pass: per-cell
+clock windows), and summarises the launches with :mod:`stats`.
 
 plain_k_sweep      Section 3 / Section 4.2: fixed-work K sweep at several
                    occupancies, ascending and reversed order.
