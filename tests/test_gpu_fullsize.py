@@ -68,6 +68,36 @@ def test_k_sweep_full_size(c2, w, policy):
     assert oplan.kset_mismatch(issued) <= 0.0246 / 100
 
 
+def test_bench_sweep_graph_full_size(c2):
+    """The exact timed configuration of the bench: the 1 GiB K sweep at 4..32
+    waves per CU, ascending then reversed, cache policy sc1+nt, captured into
+    one graph and replayed.  Every cell's global sinks equal the oracle's
+    checksum of the vectors it issues (a prefix of the buffer: 64*K*Q <=
+    2**26 vectors, no wrap), on every replay."""
+    buf, nbytes, seed, _whole = c2
+    L = 1 << 26
+    cells, meta = sweeps.plain_k_cells(buf, nbytes, L, isw.CACHE_BYPASS_L1_NT,
+                                       [4 * w for w in range(1, 9)], range(1, 17))
+    cells, meta, dropped = sweeps.drop_infeasible(cells, meta)
+    assert len(cells) == 252 and len(dropped) == 4
+    words = splitmix.buffer_words(seed, nbytes)
+    prefix = {}
+    g = isw.sweep_graph_create(cells)
+    try:
+        for rep in range(2):
+            res, ms = isw.sweep_graph_launch(g)
+            assert ms > 0
+            for m, r in zip(meta, res):
+                n_vec = r["issued_loads"]
+                assert n_vec == oplan.wave_group(L, m["K"], r["waves"])["issued"]
+                if n_vec not in prefix:
+                    prefix[n_vec] = checksums.whole_buffer(words[: n_vec * 4])
+                assert (r["sum32"], r["xor32"]) == prefix[n_vec], (rep, m)
+                assert r["window_ns"] > 0 and r["event_ms"] == 0
+    finally:
+        isw.sweep_graph_destroy(g)
+
+
 def test_orders_give_identical_results(c2):
     buf, nbytes, _seed, _whole = c2
     L = 1 << 26
