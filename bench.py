@@ -27,8 +27,8 @@ Reported beside it:
                 autotuned graph-batched sweep, precision sums, latency
                 ladder, order/footprint and regime map (--no-extras skips)
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build measures one
-GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark measures
+one GPU.
 """
 import argparse
 import hashlib
@@ -169,9 +169,10 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the path is single-GPU (each GPU would "
-              "stream its own HBM; see the sharding note in DESIGN.md); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the path is single-GPU (several GPUs "
+              "would each stream their own HBM and combine 16 bytes of sinks and "
+              "window end points per cell at the end); run with --gpus 1",
+              file=sys.stderr)
         return 2
 
     import torch

@@ -56,7 +56,7 @@ extern "C" {
 #define SWEEP_ENODEV     -6   /* no usable gfx950 device                     */
 
 /* ------------------------------------------------------------- work modes */
-/* Fixed work (this build's control): Q = floor(L / (64 K)) wave-groups dealt
+/* Fixed work (the library's control): Q = floor(L / (64 K)) wave-groups dealt
  * round robin, so issued loads 64 K Q match L to within 64 K - 1 loads. */
 #define SWEEP_FIXED_WORK        0
 /* Baseline arm of Section 4.2, Table 1: every wave runs `fixed_iters`

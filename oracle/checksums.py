@@ -2,7 +2,7 @@
 
 What the method computes (Section 3, "Instruments" and "The axis K"): every
 thread issues K independent loads per iteration, and every loaded word is
-folded into a sink.  This build keeps two sinks per lane, a wrapping 32-bit
+folded into a sink.  The sweep keeps two sinks per lane, a wrapping 32-bit
 sum and a 32-bit XOR, and reduces them over the lanes of a wave and over
 the grid with the same two operators.  Both operators are associative and
 commutative, so the result depends only on WHICH words each lane loads.

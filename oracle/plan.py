@@ -11,7 +11,7 @@ Three ways of turning (L, K, grid) into work are written out here:
 
 ``per_thread_floor``  the paper's construction: every thread runs
                       floor(L / (threads * K)) iterations of K loads.
-``wave_group``        this build's fixed-work mode: the work unit is a
+``wave_group``        the library's fixed-work mode: the work unit is a
                       wave-group (one wavefront's K coalesced 64-lane
                       loads), Q = floor(L / (64 K)) groups are dealt to the
                       waves round-robin, so iteration counts differ by at
