@@ -568,3 +568,44 @@ def test_concurrent_callers_get_their_own_results():
         assert got[i] == {want[i]}, i
     assert errs["codes"] == {isw.EINVAL} and errs["msg"]
     assert errs[0] == b"" and errs[1] == b""
+
+
+def test_entry_points_honour_the_callers_stream():
+    """Every entry point runs on the stream it is given: work queued on a
+    side stream (a fill, then the sweeps, without host synchronisation in
+    between) sees the fill, and gives the default stream's results."""
+    nbytes = 8 << 20
+    side = torch.cuda.Stream()                 # default priority
+    buf = dev_bytes(nbytes)
+    torch.cuda.synchronize()
+    isw.sweep_fill_u32(buf, nbytes, SEED + 50, stream=side)
+    o = isw.make_opts(stream=side, cache_policy=isw.CACHE_NT)
+    r = isw.sweep_plain(buf, nbytes, 4, 16, 8, nbytes // 16, o)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 50, nbytes))
+    assert (r["sum32"], r["xor32"]) == want
+    # refill on the side stream, then a sweep, a graph replay, two streams
+    isw.sweep_fill_u32(buf, nbytes, SEED + 51, stream=side)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 51, nbytes))
+    cells = [isw.make_cell(buf, nbytes, K, 16, 16, nbytes // 16) for K in (1, 2, 8)]
+    assert all((x["sum32"], x["xor32"]) == want for x in isw.sweep_run(cells, o))
+    g = isw.sweep_graph_create(cells)
+    try:
+        isw.sweep_fill_u32(buf, nbytes, SEED + 52, stream=side)
+        res, _ = isw.sweep_graph_launch(g, stream=side)
+    finally:
+        isw.sweep_graph_destroy(g)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 52, nbytes))
+    assert all((x["sum32"], x["xor32"]) == want for x in res)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 53, stream=side)
+    words = splitmix.buffer_words(SEED + 53, nbytes)
+    a, b = isw.sweep_two_stream_kind(buf, nbytes, 4, 2, 2, isw.KIND_PLAIN, nbytes // 16, o)
+    half = words.size // 2
+    assert (a["sum32"], a["xor32"]) == checksums.whole_buffer(words[:half])
+    assert (b["sum32"], b["xor32"]) == checksums.whole_buffer(words[half:])
+    # a payload written on the side stream and summed there
+    x = torch.full((1 << 20,), 0.5, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        x.fill_(0.25)
+    s, _ = isw.sweep_reduce_fp(x, x.numel(), isw.F32, 8, o)
+    assert s == 0.25 * x.numel()
