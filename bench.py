@@ -287,6 +287,7 @@ def main():
         "paper_like_cell": None if w4 is None else {
             "waves_per_cu": 16, "median_gbps": w4["median_gbps"],
             "peak_K": w4["peak_K"], "decline_2_8": w4.get("decline_2_8"),
+            "paired_declines_2_8": sorted(round(x, 4) for x in w4.get("paired_declines_2_8", [])),
             "regime": w4["regime"], "by_order": w4["by_order"]},
         "curves": {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
                        "pct_of_best_cell": {k: round(100 * v / summ["peak_gbps"], 1)
