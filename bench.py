@@ -290,8 +290,11 @@ def main():
             "paired_declines_2_8": sorted(round(x, 4) for x in w4.get("paired_declines_2_8", [])),
             "regime": w4["regime"], "by_order": w4["by_order"]},
         "curves": {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                       "min_gbps": {k: round(v, 1) for k, v in c["min_gbps"].items()},
+                       "best_gbps": {k: round(v, 1) for k, v in c["best_gbps"].items()},
                        "pct_of_best_cell": {k: round(100 * v / summ["peak_gbps"], 1)
                                             for k, v in c["median_gbps"].items()},
+                       "in_flight_mib": {k: v / 2**20 for k, v in c["in_flight_bytes"].items()},
                        "littles_law_latency_ns": {k: round(v, 1) for k, v in
                                                   c["implied_latency_ns"].items()},
                        "peak_K": c["peak_K"], "knee_K": c["knee_K"],
