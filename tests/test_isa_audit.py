@@ -145,3 +145,26 @@ def test_no_kernel_spills_or_uses_scratch(src):
         m = _meta(text, n)
         assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0, n
         assert m["private_segment_fixed_size"] == 0, n
+
+
+@pytest.fixture(scope="module")
+def misc():
+    t = _asm("kernels_misc")
+    return t, _functions(t)
+
+
+@pytest.mark.parametrize("DT", [0, 1, 2])
+@pytest.mark.parametrize("NL", [4, 8])
+def test_reduce_loop_keeps_all_its_loads_in_flight(misc, DT, NL):
+    """The streaming sum issues all NL 16-byte loads of a wave-group before
+    the first wait, so NL x 1 KiB per wave is in flight."""
+    text, funcs = misc
+    name = f"_ZN3ilp9reduce_fpILi{DT}ELi{NL}EEEvNS_10ReduceArgsE"
+    body = _loop(funcs[name])
+    assert body is not None, name
+    loads = [i for i, l in enumerate(body) if LOAD.match(l)]
+    assert len(loads) == NL, (name, len(loads))
+    waits = [i for i, l in enumerate(body) if l.startswith("s_waitcnt") and "vmcnt" in l]
+    assert waits and waits[0] > loads[-1]
+    m = _meta(text, name)
+    assert m["vgpr_spill_count"] == 0 and m["private_segment_fixed_size"] == 0
