@@ -131,6 +131,33 @@ def test_residency_is_pinned(c2):
         assert counts[0] == counts[-1] == w // 4
 
 
+@pytest.mark.parametrize("V,K", [(4, 3), (8, 5)])
+def test_vector_indices_past_2_to_32(V, K):
+    """A 20 GiB buffer read in 4- and 8-byte vectors: vector indices exceed
+    2**32 (V = 4) and byte offsets exceed 2**34; the work wraps past the end.
+    Sampled waves, including the last one, are recomputed from the seed."""
+    size = 20 * GIB
+    seed = sweeps.SEED_BASE + 2
+    buf = sweeps.device_buffer(size, seed)
+    n_vec = size // V
+    L = n_vec + 64 * K * 12345 + 17           # more than one pass, ragged
+    w = 8
+    try:
+        ro = recs(256 * w)
+        r = isw.sweep_plain(buf, size, K, V, w, L,
+                            isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1_NT, wave_out=ro))
+        p = oplan.wave_group(L, K, r["waves"])
+        assert r["issued_loads"] == p["issued"] and p["issued"] > n_vec
+        rr = decode_recs(ro)
+        for wave in _sample(r["waves"], k=1, seed=V):
+            want = checksums.wave_from_seed(seed, V, K, p["Q"], r["waves"], wave,
+                                            buffer_bytes=size)
+            assert (rr["sum32"][wave], rr["xor32"][wave]) == want, wave
+    finally:
+        del buf
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("size", [512 << 20, 20 * GIB])
 def test_allocation_sweep_full_size(size):
     seed = sweeps.SEED_BASE + 2
