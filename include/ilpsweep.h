@@ -127,7 +127,8 @@ typedef struct {
   uint32_t grid_wgs, wg_threads, waves;
   uint32_t iters_min, iters_max;   /* per-wave iteration counts            */
   uint32_t max_wgs_per_cu; /* residency limit of the kernel at this launch */
-  uint32_t vgprs, sgprs, lds_bytes, scratch_bytes; /* kernel resources     */
+  uint32_t vgprs, sgprs, lds_bytes, scratch_bytes; /* kernel resources;
+                                      sgprs is 0: the runtime does not report it */
   uint64_t window_ticks;   /* max(t1) - min(t0) over all waves             */
   double   window_ns;      /* window_ticks converted with the clock rate   */
   double   event_ms;       /* hipEvent time of the kernel's dispatch       */
