@@ -292,3 +292,25 @@ def test_precision_sum_full_size(kind):
               f"({res['gbps']:.0f} GB/s)")
         terms = reduce_lane_terms(kind, n, res["waves"], w)
         assert err <= fpsum.sum2_bound(absx, terms, 8, res["grid_wgs"])
+
+
+def test_chase_full_size():
+    """The latency ladder's largest footprint (2 GiB, 128-byte nodes): three
+    runs of 8192 hops, each continuing the chain where the previous stopped,
+    land where the oracle's walk of the same chain lands."""
+    from oracle import chase
+    footprint, stride = 2 * GIB, 128
+    chain, start = synth.chase_chain(footprint, stride, seed=sweeps.SEED_BASE + 8,
+                                     device="cuda")
+    words = chain.view(torch.int32).cpu().numpy()
+    try:
+        idx = start
+        for _ in range(3):
+            r = isw.sweep_chase(chain, footprint, idx, 0, 8192, isw.CACHE_BYPASS_L1)
+            want = chase.follow(words, idx, 8192)
+            assert r["final_index"] == want
+            assert 100 < r["ns_per_hop"] < 5000
+            idx = r["final_index"]
+    finally:
+        del chain
+        torch.cuda.empty_cache()
