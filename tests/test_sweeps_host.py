@@ -60,3 +60,14 @@ def test_summarize_k_sweep_discloses_a_slow_launch():
     a = s["anomalous_launches"]
     assert a["count"] == 1 and a["launches"] == 15
     assert a["worst"] == {"waves_per_cu": 8, "K": 2, "gbps": 3000.0, "ratio": 0.5}
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU and says so for --gpus N > 1 (no GPU used)."""
+    import subprocess
+    import sys
+    from conftest import ROOT
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and r.stdout == ""
+    assert "one GPU" in r.stderr
