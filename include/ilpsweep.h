@@ -25,8 +25,8 @@
  *    function says otherwise.
  *  - The library allocates small internal device scratch (per-wave records,
  *    per-cell results) on first use per device and frees it in
- *    sweep_shutdown().  Calls on one device from several host threads must
- *    be serialised by the caller.
+ *    sweep_shutdown().  Entry points take one library-wide lock, so calls
+ *    from several host threads are safe; they run one after another.
  *  - Work unit: a wave-group is one wavefront's K loads, each a contiguous,
  *    coalesced 64-lane segment of 64 * vec_width bytes.  Lane l of load j of
  *    wave-group q reads vector ((q*K + j)*64 + l) mod (bytes / vec_width).
