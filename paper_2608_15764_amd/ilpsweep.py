@@ -351,11 +351,19 @@ def sweep_batched(cells, opts=None, raw=False):
 
 
 class SweepGraph:
-    """Handle of a captured sweep: the C handle and its cell count."""
+    """Handle of a captured sweep: the C handle and its cell count.  Usable
+    as a context manager that destroys the graph on exit."""
 
     def __init__(self, handle, n):
         self.handle = handle
         self.n = n
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        sweep_graph_destroy(self)
+        return False
 
 
 def sweep_graph_create(cells, opts=None):

@@ -508,6 +508,16 @@ def test_persistent_graph_replays():
     isw.sweep_graph_destroy(g)          # a destroyed handle is cleared, not freed twice
 
 
+def test_graph_handle_as_context_manager():
+    nbytes = 1 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 60)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 60, nbytes))
+    with isw.sweep_graph_create([isw.make_cell(buf, nbytes, 2, 16, 4, nbytes // 16)]) as g:
+        res, _ = isw.sweep_graph_launch(g)
+    assert (res[0]["sum32"], res[0]["xor32"]) == want and g.handle is None
+
+
 def test_persistent_graph_rejects_bad_cells():
     nbytes = 1 << 20
     buf = dev_bytes(nbytes)
