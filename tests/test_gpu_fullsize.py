@@ -158,6 +158,37 @@ def test_vector_indices_past_2_to_32(V, K):
         torch.cuda.empty_cache()
 
 
+def test_allocation_sweep_graph_full_size():
+    """The allocation sweep as the bench runs it: one captured graph over
+    allocation x occupancy x K x order, 16 GiB issued per cell.  512 MiB and
+    2 GiB are whole numbers of passes (32 and 8), so every cell's sinks have
+    a closed form: (passes x S mod 2**32, 0)."""
+    seed = sweeps.SEED_BASE + 2
+    sizes = [512 << 20, 2 * GIB]
+    buf = sweeps.device_buffer(max(sizes), seed)
+    L = 1 << 30
+    try:
+        cells, meta = [], []
+        for size in sizes:
+            c, m = sweeps.plain_k_cells(buf, size, L, isw.CACHE_BYPASS_L1, [16, 32],
+                                        (1, 2, 4, 8))
+            cells += c
+            meta += [dict(x, bytes=size) for x in m]
+        want = {}
+        for size in sizes:
+            S, _X = checksums.whole_buffer(splitmix.buffer_words(seed, size))
+            want[size] = (((L * 16 // size) * S) & 0xFFFFFFFF, 0)
+        with isw.sweep_graph_create(cells) as g:
+            for rep in range(2):
+                res, _ = isw.sweep_graph_launch(g)
+                for m, r in zip(meta, res):
+                    assert r["issued_loads"] == L
+                    assert (r["sum32"], r["xor32"]) == want[m["bytes"]], (rep, m)
+    finally:
+        del buf
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("size", [512 << 20, 20 * GIB])
 def test_allocation_sweep_full_size(size):
     seed = sweeps.SEED_BASE + 2
