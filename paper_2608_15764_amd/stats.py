@@ -119,6 +119,41 @@ def anomalous_launches(samples, frac=0.9):
     return out
 
 
+def front_duplicates(blocked, K, n_waves, Q, n_vec, max_iters=64):
+    """Share of the loads of one lock-step iteration that read a segment
+    another wave reads in the same iteration.
+
+    Model of the f3 ordering experiment: every wave runs its i-th iteration
+    at the same time.  In round-robin order wave w takes group
+    q = i * n_waves + w, in blocked order q = w * G + i (G = ceil(Q /
+    n_waves)); a group starts at vector (q * K * 64) mod n_vec.  When the
+    volume wraps the allocation, groups of different waves can start at the
+    same vector, and those loads meet the data in a cache.  Averaged over up
+    to ``max_iters`` iterations spread evenly over the run.  Assumes n_vec is
+    a multiple of 64 * K (aligned groups), as in every cell measured."""
+    import numpy as np
+    if Q <= 0 or n_waves <= 0:
+        return 0.0
+    G = -(-Q // n_waves)
+    n_it = G
+    its = np.unique(np.linspace(0, n_it - 1, min(n_it, max_iters)).astype(np.int64))
+    w = np.arange(n_waves, dtype=np.int64)
+    total = dup = 0
+    for i in its:
+        if blocked:
+            q = w * G + i
+            q = q[(q < Q) & (i < G)]
+        else:
+            q = i * n_waves + w
+            q = q[q < Q]
+        if q.size == 0:
+            continue
+        starts = (q * K * 64) % n_vec
+        total += q.size
+        dup += q.size - np.unique(starts).size
+    return dup / total if total else 0.0
+
+
 def summarize_curve(samples):
     """Summary of one response curve {K: [GB/s per launch]}."""
     med = per_k_medians(samples)

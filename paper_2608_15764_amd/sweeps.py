@@ -488,7 +488,12 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
             runs = [isw.sweep_run(arr) for _ in range(n)]
             summ = summarize_k_sweep(meta, runs)
             c = summ["curves"][waves_per_cu]
+            n_waves = runs[0][0]["waves"]
             row[oname] = {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                          "front_duplicates": {
+                              K: round(stats.front_duplicates(
+                                  order == isw.ORDER_BLOCKED, K, n_waves, L // (64 * K),
+                                  size // 16), 4) for K in Ks},
                           "decline_2_8": c.get("decline_2_8"),
                           "by_order": c["by_order"],
                           "residency_flags": summ["residency_flags"],

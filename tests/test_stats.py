@@ -106,3 +106,31 @@ def test_anomalous_launches_are_disclosed():
     assert c["launches"] == 20 and c["anomalous"] == [(2, 50.0, 0.5)]
     assert c["median_gbps"][2] == 100.0            # medians are insensitive
     assert stats.anomalous_launches({4: [10.0, 10.0, 8.0]}, frac=0.85) == [(4, 8.0, 0.8)]
+
+
+def test_front_duplicates_closed_forms():
+    # round robin: the front of one iteration is contiguous, n_waves groups;
+    # no sharing while it fits the allocation
+    assert stats.front_duplicates(False, 2, 8, 64, 64 * 2 * 16) == 0.0
+    # blocked over 4 passes: wave w reads groups 4w..4w+3 of a 4-group
+    # allocation, so in every iteration all four waves read the same group
+    assert stats.front_duplicates(True, 1, 4, 16, 64 * 4) == 0.75
+    # round robin with a front of 8 groups over a 4-group allocation: each
+    # segment is read twice per iteration
+    assert stats.front_duplicates(False, 1, 8, 64, 64 * 4) == 0.5
+
+
+def test_front_duplicates_matches_brute_force():
+    from oracle import plan as oplan
+    for blocked, K, nw, Q, nv in [(False, 3, 5, 47, 64 * 3 * 4), (True, 3, 5, 47, 64 * 3 * 4),
+                                  (True, 2, 6, 100, 64 * 2 * 10), (False, 1, 16, 40, 64 * 7)]:
+        order = oplan.BLOCKED if blocked else oplan.ROUND_ROBIN
+        lists = [list(oplan.groups_of_wave(w, Q, nw, order)) for w in range(nw)]
+        n_it = max(len(x) for x in lists)
+        total = dup = 0
+        for i in range(n_it):
+            qs = [x[i] for x in lists if i < len(x)]
+            starts = [(q * K * 64) % nv for q in qs]
+            total += len(qs)
+            dup += len(qs) - len(set(starts))
+        assert stats.front_duplicates(blocked, K, nw, Q, nv, max_iters=10**6) == dup / total
