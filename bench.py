@@ -353,6 +353,8 @@ def main():
                                                    c16.get("median_gbps", {}).items()}}
         result["policy_curves"] = pc
         result["baseline_fixed_iterations"] = sweeps.fixed_iteration_arm(buf, nbytes)
+        result["completion_spread"] = sweeps.completion_spread(
+            buf, nbytes, L, isw.POLICY_NAMES[a.policy], waves_list, K=4)
         result["streaming_gate"] = sweeps.streaming_gate(buf, nbytes)
     if not a.no_cpu_baseline:
         ks_best = sorted({m["K"] for m in meta if m["waves_per_cu"] == best_w})

@@ -449,6 +449,10 @@ def test_sweep_drivers_run_small():
     for kind, w in fixed.items():
         assert ps2[kind]["waves_per_cu"] == w and ps2[kind]["tuning_gbps"] == {}
         assert ps2[kind]["sum"] == ps[kind]["sum"] or ps[kind]["waves_per_cu"] != w
+    cs = sweeps.completion_spread(buf, nbytes, nbytes // 16, isw.CACHE_NT, [4, 16], K=2, reps=1)
+    for v in cs.values():
+        assert 0 <= v["end_p10"] <= v["end_p50"] <= v["end_p90"] <= 1
+        assert v["xcd_last_end_max"] == pytest.approx(1.0) and v["last_start"] < 1
     fi = sweeps.fixed_iteration_arm(buf, nbytes, Ks=(1, 2), waves_per_cu=8, n=1)
     assert fi["issued_bytes"][2] == 2 * fi["issued_bytes"][1]
     sg = sweeps.streaming_gate(buf, nbytes, launches=3)
