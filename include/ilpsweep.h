@@ -306,8 +306,10 @@ int sweep_two_stream_kind(const void* buf, size_t bytes, int depth, int waves_a,
 int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
               sweep_result_t* results);
 
-/* Batched sweep: the same cells captured into a hipGraph (one kernel node
- * per cell, then one finishing node) and launched with a single
+/* Batched sweep (no passage of the paper defines it: it batches the cells
+ * of Section 3's sweeps the way a production sweep runs them): the same
+ * cells captured into a hipGraph (one kernel node per cell, then one
+ * finishing node) and launched with a single
  * hipGraphLaunch; equivalent to sweep_graph_create + sweep_graph_launch +
  * sweep_graph_destroy.  Per-cell windows come from the in-kernel clock
  * records; results[i].event_ms is 0 and *graph_ms receives the hipEvent
@@ -315,8 +317,9 @@ int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
 int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
                   sweep_result_t* results, double* graph_ms);
 
-/* A sweep captured once into a hipGraph and replayed: one kernel node per
- * cell, in order, then one finishing kernel.  The graph owns its scratch
+/* A sweep captured once into a hipGraph and replayed (as sweep_batched, no
+ * passage of the paper defines it): one kernel node per cell, in order,
+ * then one finishing kernel.  The graph owns its scratch
  * (wave records, per-cell results, offsets; 32 B per wave plus 40 B per
  * cell), so other library calls between replays do not disturb it.  The
  * cells' buffers must stay allocated until the graph is destroyed; their
@@ -337,8 +340,10 @@ int sweep_graph_launch(sweep_graph_t* graph, void* stream, sweep_result_t* resul
                        double* graph_ms);
 int sweep_graph_destroy(sweep_graph_t* graph);
 
-/* Autotuner: times every candidate (vec_width, K, waves_per_cu) for a plain
- * cell over `buf` / `bytes` (one full pass per launch, fixed work), `reps`
+/* Autotuner (no passage of the paper defines it; it searches the axes the
+ * method sweeps, Section 3 "The axis K" and occupancy): times every
+ * candidate (vec_width, K, waves_per_cu) for a plain cell over `buf` /
+ * `bytes` (one full pass per launch, fixed work), `reps`
  * launches each after one warm-up launch, and returns the candidate with
  * the best median bandwidth in *best (kind, K, vec_width, waves_per_cu,
  * cache_policy filled; buf, bytes and total_logical_loads set for one full
@@ -353,7 +358,9 @@ int sweep_autotune(const void* buf, size_t bytes,
                    int cache_policy, int reps,
                    sweep_cell_t* best, double* best_gbps);
 
-/* Streaming sum of a floating-point payload (precision variant): every lane
+/* Streaming sum of a floating-point payload (precision variant; no passage
+ * of the paper defines it: it applies the streaming loop of Section 3 to
+ * FP payloads and adds compensated accumulation): every lane
  * loads 16-byte vectors, decodes them to FP32 and accumulates them with
  * TwoSum into an (s, c) pair (Sum2 of Ogita, Rump and Oishi, 2005; FP8 in
  * chunks of 64 values, whose FP32 sum is exact); pairs are merged per wave
