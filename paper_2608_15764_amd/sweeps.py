@@ -165,7 +165,9 @@ def completion_spread(buf, nbytes, L, policy, waves_list, K=4, reps=3):
     window (from the per-wave clock records), per occupancy: the 10th, 50th
     and 90th percentile of the wave end times, the earliest and latest last
     end over the XCDs, and the latest wave start.  Every wave has the same
-    share of the work, so a spread of end times is unequal service."""
+    share of the work, so a spread of end times is unequal service; the
+    mean wave duration per XCD against the chip mean shows whether that
+    service differs by XCD."""
     import numpy as np
     dt = np.dtype([("sum32", "<u4"), ("xor32", "<u4"), ("hw_id", "<u4"),
                    ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
@@ -173,7 +175,7 @@ def completion_spread(buf, nbytes, L, policy, waves_list, K=4, reps=3):
     for w in waves_list:
         n = isw.sweep_device_info()["num_cus"] * w
         rec = torch.zeros(n * dt.itemsize, dtype=torch.uint8, device="cuda")
-        rows = []
+        rows, per_xcd = [], []
         for _ in range(reps + 1):                  # the first launch is the warm-up
             r = isw.sweep_plain(buf, nbytes, K, 16, w, L,
                                 isw.make_opts(cache_policy=policy, wave_out=rec))
@@ -183,13 +185,18 @@ def completion_spread(buf, nbytes, L, policy, waves_list, K=4, reps=3):
             base, win = t0.min(), max(int(t1.max() - t0.min()), 1)
             ends = (t1 - base) / win
             xcc = a["xcc_id"] & 0xF
-            last = [ends[xcc == x].max() for x in np.unique(xcc)]
+            xs = np.unique(xcc)
+            last = [ends[xcc == x].max() for x in xs]
+            dur = (t1 - t0).astype(np.float64)
+            per_xcd.append([dur[xcc == x].mean() / dur.mean() for x in xs])
             rows.append((np.percentile(ends, 10), np.median(ends), np.percentile(ends, 90),
                          min(last), max(last), ((t0 - base) / win).max(), r["gbps"]))
         m = np.median(np.array(rows[1:]), axis=0)
+        px = np.median(np.array(per_xcd[1:]), axis=0)
         out[w] = {"K": K, "end_p10": round(m[0], 3), "end_p50": round(m[1], 3),
                   "end_p90": round(m[2], 3), "xcd_last_end_min": round(m[3], 3),
                   "xcd_last_end_max": round(m[4], 3), "last_start": round(m[5], 3),
+                  "xcd_mean_duration_ratio": [round(v, 3) for v in px],
                   "gbps": round(m[6], 1)}
     return out
 

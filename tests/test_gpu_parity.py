@@ -453,6 +453,7 @@ def test_sweep_drivers_run_small():
     for v in cs.values():
         assert 0 <= v["end_p10"] <= v["end_p50"] <= v["end_p90"] <= 1
         assert v["xcd_last_end_max"] == pytest.approx(1.0) and v["last_start"] < 1
+        assert len(v["xcd_mean_duration_ratio"]) == 8
     fi = sweeps.fixed_iteration_arm(buf, nbytes, Ks=(1, 2), waves_per_cu=8, n=1)
     assert fi["issued_bytes"][2] == 2 * fi["issued_bytes"][1]
     sg = sweeps.streaming_gate(buf, nbytes, launches=3)
