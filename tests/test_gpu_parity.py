@@ -624,3 +624,16 @@ def test_entry_points_honour_the_callers_stream():
         x.fill_(0.25)
     s, _ = isw.sweep_reduce_fp(x, x.numel(), isw.F32, 8, o)
     assert s == 0.25 * x.numel()
+
+
+def test_unpinned_occupancy_gives_the_same_sinks():
+    """Residency pinning only pads LDS; the sinks do not depend on it."""
+    nbytes = 4 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 70)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 70, nbytes))
+    for w in (4, 16, 32):
+        a = isw.sweep_plain(buf, nbytes, 2, 16, w, nbytes // 16, isw.make_opts(pin_occupancy=True))
+        b = isw.sweep_plain(buf, nbytes, 2, 16, w, nbytes // 16, isw.make_opts(pin_occupancy=False))
+        assert (a["sum32"], a["xor32"]) == (b["sum32"], b["xor32"]) == want
+        assert a["lds_bytes"] > 0 and b["lds_bytes"] == 0 and a["waves"] == b["waves"]
