@@ -120,6 +120,59 @@ def _cpu_model():
     return None
 
 
+_WORDS = None
+
+
+def _oracle_cell(task):
+    """One cell's global sinks from the oracle (runs in a worker process)."""
+    from oracle import checksums, plan as oplan
+    K, n_waves, L = task
+    p = oplan.wave_group(L, K, n_waves)
+    s, x = checksums.per_wave(_WORDS, 16, K, p["Q"], n_waves)
+    return K, checksums.combine(s, x)
+
+
+def cpu_oracle_worker(spec):
+    """Child-process side of the multi-process CPU baseline: never imports
+    torch and never touches the GPU; forks its pool workers from here."""
+    global _WORDS
+    import multiprocessing as mp
+    from oracle import splitmix
+    a = json.loads(spec)
+    t0 = time.perf_counter()
+    _WORDS = splitmix.buffer_words(a["seed"], a["nbytes"])
+    t1 = time.perf_counter()
+    tasks = [(K, a["n_waves"], a["L"]) for K in a["Ks"]]
+    with mp.get_context("fork").Pool(a["procs"]) as pool:
+        res = pool.map(_oracle_cell, tasks, chunksize=1)
+    t2 = time.perf_counter()
+    print(json.dumps({"sinks": {str(K): list(v) for K, v in res},
+                      "generate_s": t1 - t0, "checksum_s": t2 - t1, "procs": a["procs"]}))
+    return 0
+
+
+def cpu_baseline_multi(seed, nbytes, L, Ks, n_waves, gpu_sinks, issued_bytes):
+    """The same oracle over the same cells, one cell per worker process, in
+    a child process started for it (the measuring process keeps the GPU)."""
+    import subprocess
+    procs = max(1, min(16, os.cpu_count() or 1, len(Ks)))
+    spec = json.dumps({"seed": seed, "nbytes": nbytes, "L": L, "Ks": list(Ks),
+                       "n_waves": n_waves, "procs": procs})
+    try:
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                            "--cpu-oracle-worker", spec], cwd=ROOT, capture_output=True,
+                           text=True, timeout=300)
+        out = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:          # reported, never fatal for the bench line
+        return {"error": f"{type(e).__name__}: {e}"}
+    ok = all(tuple(out["sinks"][str(K)]) == gpu_sinks[K] for K in Ks)
+    return {"value": issued_bytes / out["checksum_s"] / 1e9, "unit": "GB/s",
+            "cores": out["procs"], "checksum_s": out["checksum_s"],
+            "generate_s": out["generate_s"], "matches_gpu": ok,
+            "sample": "the same cells, one per worker process (fork pool in a child "
+                      "process); buffer generation excluded"}
+
+
 def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
     """Oracle per-wave checksums of one occupancy's whole K curve (one full
     cell per K), timed on the host and checked against the GPU's records."""
@@ -148,6 +201,9 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
         ok = ok and bool(np.array_equal(s, recs["sum32"]) and np.array_equal(x, recs["xor32"])
                          and p["issued"] == r["issued_loads"])
     t2 = time.perf_counter()
+    multi = cpu_baseline_multi(buf_seed, nbytes, L, Ks, gpu[Ks[0]][0]["waves"],
+                               {K: (gpu[K][0]["sum32"], gpu[K][0]["xor32"]) for K in Ks},
+                               issued)
     return {
         "value": issued / (t2 - t1) / 1e9,
         "unit": "GB/s",
@@ -162,10 +218,13 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
         "host_cores_available": os.cpu_count(),
         "host_cpu": _cpu_model(),
         "matches_gpu": ok,
+        "multi_process": multi,
     }
 
 
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--cpu-oracle-worker":
+        return cpu_oracle_worker(sys.argv[2])
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:

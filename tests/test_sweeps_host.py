@@ -71,3 +71,24 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and r.stdout == ""
     assert "one GPU" in r.stderr
+
+
+def test_bench_cpu_oracle_worker():
+    """The multi-process CPU baseline's child mode (no GPU): one cell per
+    worker, global sinks equal to the oracle's, in one JSON line."""
+    import subprocess
+    import sys
+    from conftest import ROOT
+    from oracle import checksums, plan as oplan, splitmix
+    spec = {"seed": 5, "nbytes": 4 << 20, "L": (4 << 20) // 16 + 640, "Ks": [1, 3, 5],
+            "n_waves": 96, "procs": 3}
+    r = subprocess.run([sys.executable, "bench.py", "--cpu-oracle-worker", json.dumps(spec)],
+                       cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    words = splitmix.buffer_words(5, 4 << 20)
+    for K in spec["Ks"]:
+        p = oplan.wave_group(spec["L"], K, spec["n_waves"])
+        want = checksums.combine(*checksums.per_wave(words, 16, K, p["Q"], spec["n_waves"]))
+        assert tuple(out["sinks"][str(K)]) == want
+    assert out["procs"] == 3 and out["checksum_s"] > 0
