@@ -54,7 +54,7 @@ struct TwoStreamArgs {
   uint32_t b_plain;           // 1: stream B runs the plain loop as well
 };
 
-// Precision variant: full wave-groups of 4 loads x 64 lanes x 16 bytes,
+// Precision variant: full wave-groups of 4 or 8 loads x 64 lanes x 16 bytes,
 // then the ragged remainder (whole 16-byte vectors, then the last bytes).
 struct ReduceArgs {
   const uint8_t* payload;
