@@ -226,6 +226,9 @@ def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--cpu-oracle-worker":
         return cpu_oracle_worker(sys.argv[2])
     a = parse()
+    if a.steps < 1 or a.warmup < 0:
+        print("bench.py needs --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the path is single-GPU (several GPUs "

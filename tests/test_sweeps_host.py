@@ -92,3 +92,12 @@ def test_bench_cpu_oracle_worker():
         want = checksums.combine(*checksums.per_wave(words, 16, K, p["Q"], spec["n_waves"]))
         assert tuple(out["sinks"][str(K)]) == want
     assert out["procs"] == 3 and out["checksum_s"] > 0
+
+
+def test_bench_rejects_zero_steps():
+    import subprocess
+    import sys
+    from conftest import ROOT
+    r = subprocess.run([sys.executable, "bench.py", "--steps", "0"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "--steps" in r.stderr and r.stdout == ""
