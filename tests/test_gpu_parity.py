@@ -637,3 +637,19 @@ def test_unpinned_occupancy_gives_the_same_sinks():
         b = isw.sweep_plain(buf, nbytes, 2, 16, w, nbytes // 16, isw.make_opts(pin_occupancy=False))
         assert (a["sum32"], a["xor32"]) == (b["sum32"], b["xor32"]) == want
         assert a["lds_bytes"] > 0 and b["lds_bytes"] == 0 and a["waves"] == b["waves"]
+
+
+def test_graph_survives_library_shutdown():
+    """A captured graph owns its scratch: sweep_shutdown() frees the library's
+    shared scratch but leaves the graph replayable; the library initialises
+    itself again on the next call."""
+    nbytes = 2 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 80)
+    want = checksums.whole_buffer(splitmix.buffer_words(SEED + 80, nbytes))
+    with isw.sweep_graph_create([isw.make_cell(buf, nbytes, 4, 16, 8, nbytes // 16)]) as g:
+        isw.sweep_shutdown()
+        res, _ = isw.sweep_graph_launch(g)
+        assert (res[0]["sum32"], res[0]["xor32"]) == want
+    r = isw.sweep_plain(buf, nbytes, 2, 16, 8, nbytes // 16)
+    assert (r["sum32"], r["xor32"]) == want
