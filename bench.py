@@ -265,7 +265,7 @@ def main():
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c4counters":
-        man = sweeps.lds_counter_pass(manifest=a.manifest)
+        man = sweeps.lds_counter_pass(policy=policy, manifest=a.manifest)
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c2counters":
@@ -447,15 +447,20 @@ def run_extras(a, isw, sweeps, only=None):
         nbytes = 2 * GIB
         buf = sweeps.device_buffer(nbytes, sweeps.SEED_BASE + 3)
         L = nbytes // 16
-        rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L)
-        rows["c4_two_stream"] = sweeps.two_stream(buf, nbytes, L)
+        # both paths and both streams use the swept loads' cache policy;
+        # the path comparison is repeated under every other policy beside it
+        pol = isw.POLICY_NAMES[a.policy]
+        grid = [(wa, wb) for wa in (1, 2, 4, 8) for wb in (1, 2, 4, 8)]
+        rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L, policy=pol)
+        rows["c4_path_comparison_other_policies"] = {
+            name: sweeps.path_comparison(buf, nbytes, L, policy=v)
+            for name, v in isw.POLICY_NAMES.items() if v != pol}
+        rows["c4_two_stream"] = sweeps.two_stream(buf, nbytes, L, policy=pol)
         rows["c4_two_stream_grid"] = sweeps.two_stream(
-            buf, nbytes, L, depths=(4,),
-            pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2)
+            buf, nbytes, L, depths=(4,), pairs=grid, n=2, policy=pol)
         # the section's own measurement: plain loads in both streams
         rows["c4_two_stream_same_mechanism_grid"] = sweeps.two_stream(
-            buf, nbytes, L, depths=(4,),
-            pairs=[(a, b) for a in (1, 2, 4, 8) for b in (1, 2, 4, 8)], n=2,
+            buf, nbytes, L, depths=(4,), pairs=grid, n=2, policy=pol,
             kind_b=isw.KIND_PLAIN)
         rows["c4_wall_s"] = time.perf_counter() - t
         del buf

@@ -262,7 +262,8 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
             samples.setdefault(m, []).append(r["gbps"])
             sums.setdefault(m[:2], set()).add((r["sum32"], r["xor32"]))
     # both kinds read the same map at each (waves, depth): equal sinks
-    out = {"checksums_equal_across_paths": all(len(v) == 1 for v in sums.values())}
+    out = {"checksums_equal_across_paths": all(len(v) == 1 for v in sums.values()),
+           "policy": {v: k for k, v in isw.POLICY_NAMES.items()}[policy]}
     for W in waves_list:
         row = {}
         for D in depths:
