@@ -254,7 +254,7 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
                     cells.append(isw.make_cell(buf, nbytes, D, 16, W, L, kind=kind,
                                                cache_policy=policy))
                     meta.append((W, D, kind))
-    isw.sweep_run(cells)
+    warm = isw.sweep_run(cells)
     samples = {}
     sums = {}
     for _ in range(n):
@@ -263,7 +263,10 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
             sums.setdefault(m[:2], set()).add((r["sum32"], r["xor32"]))
     # both kinds read the same map at each (waves, depth): equal sinks
     out = {"checksums_equal_across_paths": all(len(v) == 1 for v in sums.values()),
-           "policy": {v: k for k, v in isw.POLICY_NAMES.items()}[policy]}
+           "policy": {v: k for k, v in isw.POLICY_NAMES.items()}[policy],
+           # the fixed-work control carried over to the LDS paths: every
+           # depth issues 64 D floor(L / 64 D) requests of the same L
+           "depth_set_mismatch": stats.kset_mismatch([r["issued_loads"] for r in warm])}
     for W in waves_list:
         row = {}
         for D in depths:

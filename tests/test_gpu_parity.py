@@ -426,6 +426,8 @@ def test_sweep_drivers_run_small():
     assert out["checksums_consistent"] and set(out["curves"]) == {4, 32}
     pc = sweeps.path_comparison(buf, nbytes, nbytes // 16, depths=(1, 4), waves_list=(1, 4), n=1)
     assert pc["checksums_equal_across_paths"] and pc[4][4]["ratio"] > 0
+    # depths 1 and 4 both divide nbytes // 16 / 64: identical issued work
+    assert pc["depth_set_mismatch"] == 0.0
     ts = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((4, 4), (1, 2)), n=1)
     assert set(ts) == {"D4_A4_B4", "D4_A1_B2"}
     tp = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((2, 2),), n=1,
