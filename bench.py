@@ -451,7 +451,7 @@ def run_extras(a, isw, sweeps, only=None):
         # the path comparison is repeated under every other policy beside it
         pol = isw.POLICY_NAMES[a.policy]
         grid = [(wa, wb) for wa in (1, 2, 4, 8) for wb in (1, 2, 4, 8)]
-        rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L, policy=pol)
+        rows["c4_path_comparison"] = sweeps.path_comparison(buf, nbytes, L, policy=pol, n=5)
         rows["c4_path_comparison_other_policies"] = {
             name: sweeps.path_comparison(buf, nbytes, L, policy=v)
             for name, v in isw.POLICY_NAMES.items() if v != pol}

@@ -245,6 +245,10 @@ def allocation_sweep(sizes, Ks=(1, 2, 4, 8), waves_list=(16,), L=1 << 30,
 # ------------------------------------------------- path comparison (C4)
 def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8),
                     policy=isw.CACHE_DEFAULT, n=3):
+    """LDS-direct against matched register path (Section 4.3) at every
+    (waves per CU, depth).  One warm-up pass, then n passes; a pass runs
+    every depth ascending and then reversed, so each cell has 2n timed
+    launches, whose median is the cell's figure."""
     cells, meta = [], []
     for W in waves_list:
         for order in ("asc", "rev"):
@@ -266,7 +270,8 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
            "policy": {v: k for k, v in isw.POLICY_NAMES.items()}[policy],
            # the fixed-work control carried over to the LDS paths: every
            # depth issues 64 D floor(L / 64 D) requests of the same L
-           "depth_set_mismatch": stats.kset_mismatch([r["issued_loads"] for r in warm])}
+           "depth_set_mismatch": stats.kset_mismatch([r["issued_loads"] for r in warm]),
+           "launches_per_cell": 2 * n}
     for W in waves_list:
         row = {}
         for D in depths:
