@@ -423,7 +423,7 @@ def main():
         result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf)
     del buf
     if not a.no_extras:
-        result["rows"] = run_extras(a, isw, sweeps)
+        result["rows"] = run_extras(a, isw, sweeps, best_w=best_w)
     line = json.dumps(result, default=str)
     if a.json_out:
         with open(a.json_out, "w") as f:
@@ -432,15 +432,27 @@ def main():
     return 0
 
 
-def run_extras(a, isw, sweeps, only=None):
+def run_extras(a, isw, sweeps, only=None, best_w=None):
+    """The other configurations.  ``best_w`` is the K sweep's best
+    occupancy (waves per CU); without it (``--only c3``) one short pass of
+    the same K sweep finds it."""
     import torch
     rows = {}
     GIB = 1 << 30
     if only in (None, "c3"):
         t = time.perf_counter()
+        pol = isw.POLICY_NAMES[a.policy]
+        if best_w is None:
+            kbuf = sweeps.device_buffer(GIB, sweeps.SEED_BASE + 1)
+            best_w = sweeps.plain_k_sweep(kbuf, GIB, 1 << 26, pol, range(4, 33, 4),
+                                          range(1, 17), passes=2)["best_waves_per_cu"]
+            del kbuf
+        # the paper-like occupancy (4 waves/SIMD) and the K sweep's best
+        waves = (16,) if best_w == 16 else (16, best_w)
         sizes = [512 << 20, GIB, 2 * GIB, 4 * GIB, 8 * GIB, 20 * GIB]
-        rows["c3_allocation_sweep"] = sweeps.allocation_sweep(
-            sizes, waves_list=(16, 32), policy=isw.POLICY_NAMES[a.policy])
+        rows["c3_allocation_sweep"] = sweeps.allocation_sweep(sizes, waves_list=waves,
+                                                              policy=pol)
+        rows["c3_allocation_sweep"]["waves_per_cu"] = list(waves)
         rows["c3_allocation_sweep"]["wall_s"] = time.perf_counter() - t
     if only in (None, "c4"):
         t = time.perf_counter()
