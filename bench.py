@@ -92,12 +92,12 @@ def parse():
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
                     choices=["c3", "c4", "c5a", "c5b", "c3counters", "c2counters",
-                             "c4counters", "next"],
+                             "c4counters", "c4stalls", "next"],
                     help="run only one extra configuration (no K sweep); "
-                         "c3counters runs the allocation-sweep cells one launch "
+                         "the *counters modes and c4stalls run cells one launch "
                          "per call for a separate rocprofv3 counter run")
     ap.add_argument("--manifest", default=None,
-                    help="launch manifest path for --only c3counters")
+                    help="launch manifest path for the counter-run modes")
     ap.add_argument("--c5b-waves", default=None,
                     help="fixed waves per CU for the precision sums instead of "
                          "tuning, e.g. f32=8,bf16=8,fp8_e4m3=4 (for profiling "
@@ -266,6 +266,14 @@ def main():
         return 0
     if a.only == "c4counters":
         man = sweeps.lds_counter_pass(policy=policy, manifest=a.manifest)
+        print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only == "c4stalls":
+        # both LDS paths under the default policy and the swept one, for
+        # counter runs on where each path's loads wait
+        pols = sorted({isw.CACHE_DEFAULT, policy})
+        man = sweeps.lds_counter_pass(waves_list=(1, 4), depths=(8, 16), policies=pols,
+                                      manifest=a.manifest)
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c2counters":

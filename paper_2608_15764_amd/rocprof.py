@@ -199,7 +199,7 @@ def attribute(rows, manifest, kernel_substr="plain_kload"):
     return out
 
 
-CELL_KEYS = ("path", "bytes", "waves_per_cu", "K", "order")
+CELL_KEYS = ("path", "policy", "bytes", "waves_per_cu", "K", "order")
 
 
 def cell_key(m):
@@ -210,9 +210,10 @@ def cell_key(m):
 def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload",
                cus=None, xccs=None):
     """Per cell: median of every counter over the non-warm-up launches, plus
-    the derived L2 hit rate, scaled bytes and, given the device's CU and XCC
-    counts, the fraction of CU cycles the LDS was busy (SQ_LDS_IDX_ACTIVE is
-    summed over every CU; GRBM_GUI_ACTIVE over every XCC)."""
+    the derived L2 hit rate, scaled bytes, mean L1 latencies and, given the
+    device's CU and XCC counts, the fraction of CU cycles the LDS was busy
+    (SQ_LDS_IDX_ACTIVE is summed over every CU; GRBM_GUI_ACTIVE over every
+    XCC)."""
     cells = {}
     for rows in runs:
         for c, pairs in attribute(rows, manifest, kernel_substr).items():
@@ -233,6 +234,14 @@ def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload",
         gui = row.get("GRBM_GUI_ACTIVE")
         if cus and xccs and gui and "SQ_LDS_IDX_ACTIVE" in row:
             row["lds_busy_frac"] = row["SQ_LDS_IDX_ACTIVE"] / (gui / xccs * cus)
+        # mean cycles per L1-to-L2 read request, and per wave instruction
+        # in the L1 (the counters' own definitions: totals over requests
+        # or over TA state reads)
+        for name, total, count in (
+                ("tcp_tcc_read_latency", "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum"),
+                ("tcp_wave_latency", "TCP_TCP_LATENCY_sum", "TCP_TA_TCP_STATE_READ_sum")):
+            if row.get(count) and total in row:
+                row[name] = row[total] / row[count]
         table[key] = row
     return table
 

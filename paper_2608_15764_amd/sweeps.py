@@ -742,24 +742,31 @@ def k_counter_pass(nbytes=GIB, waves_list=(4, 16), Ks=(1, 2, 4, 8, 16), L=1 << 2
 
 def lds_counter_pass(nbytes=2 * GIB, waves_list=(1, 4), depths=(1, 4, 8, 16),
                      L=1 << 27, policy=isw.CACHE_DEFAULT, reps=3,
-                     seed=SEED_BASE + 3, manifest=None):
+                     seed=SEED_BASE + 3, manifest=None, policies=None):
     """The LDS-direct and matched register paths cell by cell, one launch
-    per call, for a separate rocprofv3 run with LDS counters (is the LDS
-    itself ever the limit?).  The first launch of every cell is its
-    warm-up.  Returns (and optionally writes) the launch manifest."""
+    per call, for a separate rocprofv3 counter run (is the LDS itself ever
+    the limit?  where do register loads wait?).  With ``policies`` every
+    cell runs under each of those cache policies and its manifest entries
+    name the policy.  The first launch of every cell is its warm-up.
+    Returns (and optionally writes) the launch manifest."""
     buf = device_buffer(nbytes, seed)
+    names = {v: k for k, v in isw.POLICY_NAMES.items()}
     order = []
-    for w in waves_list:
-        for D in depths:
-            for kind, path in ((isw.KIND_LDS_ASYNC, "lds_async"),
-                               (isw.KIND_LDS_MATCHED, "lds_matched")):
-                c = isw.make_cell(buf, nbytes, D, 16, w, L, kind=kind, cache_policy=policy)
-                for rep in range(reps):
-                    r = isw.sweep_run([c])[0]
-                    order.append({"path": path, "bytes": nbytes, "waves_per_cu": w,
-                                  "K": D, "order": "asc", "rep": rep, "warmup": rep == 0,
-                                  "issued_bytes": r["issued_bytes"], "gbps": r["gbps"],
-                                  "window_ns": r["window_ns"]})
+    for pol in (policies or (policy,)):
+        for w in waves_list:
+            for D in depths:
+                for kind, path in ((isw.KIND_LDS_ASYNC, "lds_async"),
+                                   (isw.KIND_LDS_MATCHED, "lds_matched")):
+                    c = isw.make_cell(buf, nbytes, D, 16, w, L, kind=kind, cache_policy=pol)
+                    for rep in range(reps):
+                        r = isw.sweep_run([c])[0]
+                        e = {"path": path, "bytes": nbytes, "waves_per_cu": w,
+                             "K": D, "order": "asc", "rep": rep, "warmup": rep == 0,
+                             "issued_bytes": r["issued_bytes"], "gbps": r["gbps"],
+                             "window_ns": r["window_ns"]}
+                        if policies:
+                            e["policy"] = names[pol]
+                        order.append(e)
     del buf
     if manifest:
         with open(manifest, "w") as f:

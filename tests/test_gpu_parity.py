@@ -441,6 +441,10 @@ def test_sweep_drivers_run_small():
                                   reps=2)
     assert len(man) == 8 and {m["path"] for m in man} == {"lds_async", "lds_matched"}
     assert all(m["issued_bytes"] > 0 and m["gbps"] > 0 for m in man)
+    assert all("policy" not in m for m in man)
+    man = sweeps.lds_counter_pass(nbytes=4 << 20, waves_list=(1,), depths=(2,), L=1 << 18,
+                                  reps=2, policies=(isw.CACHE_DEFAULT, isw.CACHE_BYPASS_L1_NT))
+    assert len(man) == 8 and {m["policy"] for m in man} == {"default", "bypass_l1_nt"}
     lad = sweeps.latency_ladder(footprints=[8 << 10, 1 << 20], hops=256, n_samples=128,
                                 evict_bytes=16 << 20)
     assert lad[8 << 10]["default"]["mean_ns"] > 0

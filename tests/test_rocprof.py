@@ -130,3 +130,27 @@ def test_lds_busy_fraction(tmp_path):
                              cus=256, xccs=8)
     # 8e6 busy CU-cycles over 1e6 cycles x 256 CUs
     assert tab[("lds_async", 1, 4, 8, "asc")]["lds_busy_frac"] == pytest.approx(8e6 / 256e6)
+
+
+def test_cell_table_keys_on_policy_and_derives_latencies(tmp_path):
+    """Manifests that name a cache policy key their cells on it; the L1
+    latency totals are divided by their request and wave counts."""
+    K = "void ilp::lds_kernel_t<2, 8, 0>(ilp::LdsArgs)"
+    man, rows = [], []
+    for pol, lat in (("default", 900.0), ("bypass_l1_nt", 600.0)):
+        for rep in range(2):
+            man.append({"path": "lds_matched", "policy": pol, "bytes": 1 << 31,
+                        "waves_per_cu": 1, "K": 8, "order": "asc", "rep": rep,
+                        "warmup": rep == 0})
+            rows += [(K, "TCP_TCC_READ_REQ_LATENCY_sum", lat * 1000),
+                     (K, "TCP_TCC_READ_REQ_sum", 1000.0),
+                     (K, "TCP_TCP_LATENCY_sum", 5000.0),
+                     (K, "TCP_TA_TCP_STATE_READ_sum", 0.0)]
+    p = tmp_path / "t_counter_collection.csv"
+    _write_cc(p, rows)
+    tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man, kernel_substr="lds_kernel_t")
+    assert set(tab) == {("lds_matched", "default", 1 << 31, 1, 8, "asc"),
+                        ("lds_matched", "bypass_l1_nt", 1 << 31, 1, 8, "asc")}
+    row = tab[("lds_matched", "default", 1 << 31, 1, 8, "asc")]
+    assert row["tcp_tcc_read_latency"] == pytest.approx(900.0)
+    assert "tcp_wave_latency" not in row           # zero state reads: no ratio
