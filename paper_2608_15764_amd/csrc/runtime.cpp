@@ -119,31 +119,25 @@ int ensure_events(Dev& d, size_t n) {
   return SWEEP_OK;
 }
 
-int init_device(int ordinal, Dev** out) {
-  auto it = g_devs.find(ordinal);
-  if (it != g_devs.end()) {
-    *out = it->second;
-    return SWEEP_OK;
-  }
-  hipDeviceProp_t prop;
-  HIP_TRY(hipGetDeviceProperties(&prop, ordinal));
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(SWEEP_ENODEV, std::string("library is built for gfx950, device is ") +
-                                  prop.gcnArchName);
-  Dev* d = new Dev();
-  d->ordinal = ordinal;
-  std::strncpy(d->arch, prop.gcnArchName, sizeof(d->arch) - 1);
-  d->num_cus = (uint32_t)prop.multiProcessorCount;
-  d->lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
-  d->lds_per_wg_max = (uint32_t)prop.sharedMemPerBlock;
-  d->l2 = (uint32_t)prop.l2CacheSize;
-  d->hbm = (uint64_t)prop.totalGlobalMem;
-  d->clock_khz = prop.clockRate;
-  d->mem_khz = prop.memoryClockRate;
-  d->bus_bits = prop.memoryBusWidth;
-  int wc_khz = 0;
-  HIP_TRY(hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, ordinal));
-  d->nominal_hz = wc_khz > 0 ? wc_khz * 1000.0 : 1.0e8;
+// Frees everything a Dev holds, then the Dev (its device is current).
+void release_device(Dev* d) {
+  if (d->rec) (void)hipFree(d->rec);
+  if (d->res) (void)hipFree(d->res);
+  if (d->res_h) (void)hipHostFree(d->res_h);
+  if (d->partials) (void)hipFree(d->partials);
+  if (d->dsum) (void)hipFree(d->dsum);
+  if (d->dsum_h) (void)hipHostFree(d->dsum_h);
+  if (d->clk) (void)hipFree(d->clk);
+  if (d->chase_out) (void)hipFree(d->chase_out);
+  if (d->offs) (void)hipFree(d->offs);
+  if (d->offs_h) (void)hipHostFree(d->offs_h);
+  for (auto e : d->ev) (void)hipEventDestroy(e);
+  if (d->capture) (void)hipStreamDestroy(d->capture);
+  delete d;
+}
+
+// Allocates the device's scratch and events; on failure frees what it got.
+int setup_device(Dev* d) {
   // scratch for the largest default grid (32 waves per CU)
   SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)d->num_cus * 32));
   SW_TRY(ensure_dev(d->res, d->res_cap, 64));
@@ -155,6 +149,39 @@ int init_device(int ordinal, Dev** out) {
   size_t chase_cap = 0;
   SW_TRY(ensure_dev(d->chase_out, chase_cap, 5));
   SW_TRY(ensure_events(*d, 8));
+  return SWEEP_OK;
+}
+
+int init_device(int ordinal, Dev** out) {
+  auto it = g_devs.find(ordinal);
+  if (it != g_devs.end()) {
+    *out = it->second;
+    return SWEEP_OK;
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ordinal));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SWEEP_ENODEV, std::string("library is built for gfx950, device is ") +
+                                  prop.gcnArchName);
+  int wc_khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, ordinal));
+  Dev* d = new Dev();
+  d->ordinal = ordinal;
+  std::strncpy(d->arch, prop.gcnArchName, sizeof(d->arch) - 1);
+  d->num_cus = (uint32_t)prop.multiProcessorCount;
+  d->lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
+  d->lds_per_wg_max = (uint32_t)prop.sharedMemPerBlock;
+  d->l2 = (uint32_t)prop.l2CacheSize;
+  d->hbm = (uint64_t)prop.totalGlobalMem;
+  d->clock_khz = prop.clockRate;
+  d->mem_khz = prop.memoryClockRate;
+  d->bus_bits = prop.memoryBusWidth;
+  d->nominal_hz = wc_khz > 0 ? wc_khz * 1000.0 : 1.0e8;
+  const int rc = setup_device(d);
+  if (rc != SWEEP_OK) {
+    release_device(d);
+    return rc;
+  }
   g_devs[ordinal] = d;
   *out = d;
   return SWEEP_OK;
@@ -392,19 +419,7 @@ int sweep_shutdown(void) {
     Dev* d = kv.second;
     (void)hipSetDevice(d->ordinal);
     (void)hipDeviceSynchronize();
-    if (d->rec) (void)hipFree(d->rec);
-    if (d->res) (void)hipFree(d->res);
-    if (d->res_h) (void)hipHostFree(d->res_h);
-    if (d->partials) (void)hipFree(d->partials);
-    if (d->dsum) (void)hipFree(d->dsum);
-    if (d->dsum_h) (void)hipHostFree(d->dsum_h);
-    if (d->clk) (void)hipFree(d->clk);
-    if (d->chase_out) (void)hipFree(d->chase_out);
-    if (d->offs) (void)hipFree(d->offs);
-    if (d->offs_h) (void)hipHostFree(d->offs_h);
-    for (auto e : d->ev) (void)hipEventDestroy(e);
-    if (d->capture) (void)hipStreamDestroy(d->capture);
-    delete d;
+    release_device(d);
   }
   g_devs.clear();
   (void)hipSetDevice(cur);
