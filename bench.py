@@ -482,6 +482,14 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         rows["c4_two_stream_same_mechanism_grid"] = sweeps.two_stream(
             buf, nbytes, L, depths=(4,), pairs=grid, n=2, policy=pol,
             kind_b=isw.KIND_PLAIN)
+        # the same streams on different CUs: twice the waves per workgroup
+        # on half of the CUs, so each stream keeps its total waves
+        split_pairs = [(2 * wa, 2 * wb) for wa, wb in grid]
+        rows["c4_two_stream_split_same_mechanism_grid"] = sweeps.two_stream(
+            buf, nbytes, L, depths=(4,), pairs=split_pairs, n=2, policy=pol,
+            kind_b=isw.KIND_PLAIN, split=True)
+        rows["c4_two_stream_split_grid"] = sweeps.two_stream(
+            buf, nbytes, L, depths=(4,), pairs=split_pairs, n=2, policy=pol, split=True)
         rows["c4_wall_s"] = time.perf_counter() - t
         del buf
     if only in (None, "c5a"):

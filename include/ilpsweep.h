@@ -296,6 +296,29 @@ int sweep_two_stream_kind(const void* buf, size_t bytes, int depth, int waves_a,
                           int waves_b, int kind_b, uint64_t total_logical_loads,
                           const sweep_opts_t* opt, sweep_result_t out[2]);
 
+/* The two streams placed on different CUs: the cross-SM placement that
+ * Section 6 lists as confirmatory work for the same-CTA test of Section
+ * 4.4.  Half of the workgroups run `waves_a` waves of stream A, the other
+ * half `waves_b` waves of stream B (workgroups of max(waves_a, waves_b)
+ * waves; the surplus waves of the smaller stream leave at once).  In every
+ * run of 16 consecutive workgroups the first 8 are stream A's and the last
+ * 8 stream B's; workgroups are dealt to the 8 XCDs in turn, so each XCD
+ * holds as many of each.  With opt->pin_occupancy (the default) each CU
+ * holds one workgroup, so no CU runs both streams.  A stream with 0 waves
+ * leaves its workgroups empty: the solo runs keep the co-run's placement.
+ * Equal total waves per stream to sweep_two_stream_kind(a, b) are
+ * sweep_two_stream_split(2a, 2b).  The buffer halves, the split of
+ * total_logical_loads, the sinks and out[] are as in sweep_two_stream_kind.
+ *   waves_a, waves_b 0..16, not both 0; the grid (opt->grid_wgs, or one
+ *   workgroup per CU) a multiple of 16, else SWEEP_EINVAL; other
+ *   arguments and errors as sweep_two_stream_kind.
+ * No passage of the paper measures this placement; it states only that
+ * its two-stream result is same-CTA and names cross-SM placement as work
+ * to do. */
+int sweep_two_stream_split(const void* buf, size_t bytes, int depth, int waves_a,
+                           int waves_b, int kind_b, uint64_t total_logical_loads,
+                           const sweep_opts_t* opt, sweep_result_t out[2]);
+
 /* Sweep driver: runs `n` cells back to back on opt->stream in the given
  * order (ascending or reversed sweeps are the caller's ordering, Section
  * 3), with per-cell hipEvents and per-wave clock windows, and one host

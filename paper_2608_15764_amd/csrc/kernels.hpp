@@ -52,6 +52,7 @@ struct TwoStreamArgs {
   uint32_t* lane_out;      // lanes of A then lanes of B, or null
   uint32_t waves_a, waves_b;  // per workgroup
   uint32_t b_plain;           // 1: stream B runs the plain loop as well
+  uint32_t split;             // 1: each workgroup runs one stream only
 };
 
 // Precision variant: full wave-groups of 4 or 8 loads x 64 lanes x 16 bytes,

@@ -8,7 +8,9 @@
 //  two_stream   one workgroup per CU whose first waves run the plain
 //               batched K-load loop over the first half of the buffer and
 //               whose last waves run either the LDS-direct ring or the
-//               same plain loop over the second.
+//               same plain loop over the second; or, split, half of the
+//               workgroups run stream A and the other half stream B, so
+//               the two streams share no CU.
 // Each wave owns `depth` 1 KiB slots of the workgroup's dynamic LDS.
 #include <array>
 #include <utility>
@@ -40,12 +42,52 @@ __global__ __launch_bounds__(1024) void lds_kernel_t(LdsArgs a) {
   wave_epilogue(s, x, t0, t1, wid, a.rec, a.lane_out);
 }
 
+// Stream B of a two-stream launch: the LDS-direct ring or the plain loop.
+template <int D, int POL>
+__device__ __forceinline__ void stream_b(const TwoStreamArgs& a, uint32_t wid,
+                                         uint32_t n_waves, uint32_t wb,
+                                         uint32_t lane, uint32_t& s, uint32_t& x) {
+  if (a.b_plain) {
+    plain_loop16<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid, n_waves,
+                         lane, s, x);
+  } else {
+    u32x4* ring = lds_ring + wb * (D * kWave);
+    async_ring_loop<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid, n_waves,
+                            lane, ring, s, x);
+  }
+}
+
 template <int D, int POL>
 __global__ __launch_bounds__(1024) void two_stream_t(TwoStreamArgs a) {
   const uint64_t t0 = wall_ticks();
   const uint32_t lane = lane_id();
   const uint32_t wv = wave_in_wg();
   uint32_t s = 0, x = 0;
+  if (a.split) {
+    // Workgroups 16m .. 16m+7 run stream A and 16m+8 .. 16m+15 stream B
+    // (the grid is a multiple of 16).  Workgroups are dealt to the 8 XCDs
+    // in turn, so every XCD holds as many workgroups of A as of B; with one
+    // workgroup per CU no CU runs both.  Waves beyond the stream's count
+    // leave at once and write no record.
+    const uint32_t g = blockIdx.x;
+    const bool is_a = ((g >> 3) & 1u) == 0;
+    const uint32_t idx = (g >> 4) * 8u + (g & 7u);   // among its stream's workgroups
+    const uint32_t n_wg = gridDim.x / 2;
+    const uint32_t w = is_a ? a.waves_a : a.waves_b;
+    if (wv >= w) return;
+    const uint32_t wid = idx * w + wv;
+    if (is_a) {
+      plain_loop16<D, POL>(a.buf_a, a.n_vec_a, a.Q_a, a.stride_a, wid,
+                           n_wg * a.waves_a, lane, s, x);
+      const uint64_t t1 = wall_ticks();
+      wave_epilogue(s, x, t0, t1, wid, a.rec, a.lane_out);
+    } else {
+      stream_b<D, POL>(a, wid, n_wg * a.waves_b, wv, lane, s, x);
+      const uint64_t t1 = wall_ticks();
+      wave_epilogue(s, x, t0, t1, n_wg * a.waves_a + wid, a.rec, a.lane_out);
+    }
+    return;
+  }
   if (wv < a.waves_a) {
     const uint32_t wid = blockIdx.x * a.waves_a + wv;
     plain_loop16<D, POL>(a.buf_a, a.n_vec_a, a.Q_a, a.stride_a, wid,
@@ -55,14 +97,7 @@ __global__ __launch_bounds__(1024) void two_stream_t(TwoStreamArgs a) {
   } else {
     const uint32_t wb = wv - a.waves_a;
     const uint32_t wid = blockIdx.x * a.waves_b + wb;
-    if (a.b_plain) {
-      plain_loop16<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid,
-                           gridDim.x * a.waves_b, lane, s, x);
-    } else {
-      u32x4* ring = lds_ring + wb * (D * kWave);
-      async_ring_loop<D, POL>(a.buf_b, a.n_vec_b, a.Q_b, a.stride_b, wid,
-                              gridDim.x * a.waves_b, lane, ring, s, x);
-    }
+    stream_b<D, POL>(a, wid, gridDim.x * a.waves_b, wb, lane, s, x);
     const uint64_t t1 = wall_ticks();
     const uint32_t base = gridDim.x * a.waves_a;
     wave_epilogue(s, x, t0, t1, base + wid, a.rec, a.lane_out);

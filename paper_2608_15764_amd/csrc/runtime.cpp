@@ -397,6 +397,115 @@ int single_cell(const sweep_cell_t& c, const sweep_opts_t* opt, sweep_result_t* 
   return SWEEP_OK;
 }
 
+// Both two-stream placements.  Same workgroup: every workgroup holds
+// waves_plain waves of stream A and waves_async of stream B.  Split: half of
+// the workgroups hold waves_plain waves of A, the other half waves_async of
+// B, in workgroups of the larger count.
+int two_stream_impl(const void* buf, size_t bytes, int depth, int waves_plain,
+                    int waves_async, int kind_b, uint64_t total_logical_loads,
+                    bool split, const sweep_opts_t* opt, sweep_result_t out[2]) {
+  if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
+  if (kind_b != SWEEP_KIND_PLAIN && kind_b != SWEEP_KIND_LDS_ASYNC)
+    return fail(SWEEP_EINVAL, "stream B runs plain loads or the LDS-direct ring");
+  const bool b_plain = kind_b == SWEEP_KIND_PLAIN;
+  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
+  if (depth < 1 || depth > 16) return fail(SWEEP_EINVAL, "depth must be in 1..16");
+  const int max_w = split ? 16 : 8;
+  if (waves_plain < 0 || waves_plain > max_w || waves_async < 0 || waves_async > max_w ||
+      waves_plain + waves_async == 0)
+    return fail(SWEEP_EINVAL, split ? "stream waves must be in 0..16, not both 0"
+                                    : "waves_plain and waves_async must be in 0..8, not both 0");
+  if (bytes == 0) return fail(SWEEP_EINVAL, "empty buffer");
+  if (bytes % 2048 || reinterpret_cast<uintptr_t>(buf) % 16)
+    return fail(SWEEP_EALIGN, "two-stream needs a 16-byte aligned buffer, bytes % 2048 == 0");
+  if (total_logical_loads == 0) return fail(SWEEP_EINVAL, "total_logical_loads is 0");
+  const int pol = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
+  if (pol < 0 || pol > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  const uint32_t grid = (opt && opt->grid_wgs) ? opt->grid_wgs : d->num_cus;
+  if (split && grid % 16)
+    return fail(SWEEP_EINVAL, "the split placement needs a grid that is a multiple of 16");
+  // workgroups per stream
+  const uint32_t wg_a = split ? grid / 2 : grid, wg_b = wg_a;
+  const uint64_t n_vec = bytes / 16, half = n_vec / 2;
+  const uint64_t La = total_logical_loads / 2, Lb = total_logical_loads - La;
+  TwoStreamArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.buf_a = static_cast<const uint8_t*>(buf);
+  a.n_vec_a = half;
+  a.buf_b = static_cast<const uint8_t*>(buf) + half * 16;
+  a.n_vec_b = n_vec - half;
+  a.waves_a = (uint32_t)waves_plain;
+  a.waves_b = (uint32_t)waves_async;
+  a.b_plain = b_plain ? 1u : 0u;
+  a.split = split ? 1u : 0u;
+  if (waves_plain) region_plan(a.n_vec_a, depth, La, wg_a * a.waves_a, &a.Q_a, &a.stride_a);
+  if (waves_async) region_plan(a.n_vec_b, depth, Lb, wg_b * a.waves_b, &a.Q_b, &a.stride_b);
+  if ((waves_plain && a.Q_a == 0) || (waves_async && a.Q_b == 0))
+    return fail(SWEEP_EINVAL, "L is smaller than one wave-group per stream");
+  const uint32_t threads =
+      (uint32_t)(split ? std::max(waves_plain, waves_async) : waves_plain + waves_async) * 64u;
+  const uint32_t ring = b_plain ? 0u : (uint32_t)waves_async * (uint32_t)depth * 1024u;
+  if (ring > d->lds_per_wg_max) return fail(SWEEP_EOCCUPANCY, "LDS ring exceeds the per-workgroup LDS");
+  size_t lds = ring;
+  if (pin_of(opt)) lds = std::max<size_t>(lds, pin_padding(1, ring, d->lds_per_cu, d->lds_per_wg_max));
+  const void* fn = two_stream_kernel(depth, pol);
+  if (!fn) return fail(SWEEP_EINVAL, "no two-stream kernel for this depth and policy");
+  hipFuncAttributes fa;
+  HIP_TRY(hipFuncGetAttributes(&fa, fn));
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds));
+  if (nb < 1) return fail(SWEEP_EOCCUPANCY, "two-stream workgroup does not fit a CU");
+  const uint32_t wa = wg_a * a.waves_a, wb = wg_b * a.waves_b;
+  SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)wa + wb));
+  SW_TRY(ensure_events(*d, 3));
+  sweep_wave_rec_t* rec = (opt && opt->wave_out) ? opt->wave_out : d->rec;
+  a.rec = rec;
+  a.lane_out = opt ? opt->lane_out : nullptr;
+  hipStream_t st = as_stream(opt);
+  SW_TRY(upload_offsets(*d, {0ull, (uint64_t)wa, (uint64_t)wa + wb}, st));
+  HIP_TRY(launch_timed(fn, grid, threads, lds, st, a, d->ev[0], d->ev[1]));
+  HIP_TRY(launch_finish_cells(rec, d->offs, 2, d->res, st));
+  HIP_TRY(hipMemcpyAsync(d->res_h, d->res, 2 * sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(d->ev[2], st));
+  HIP_TRY(hipEventSynchronize(d->ev[2]));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+  for (int s = 0; s < 2; ++s) {
+    const bool on = s == 0 ? waves_plain > 0 : waves_async > 0;
+    Prepared p;
+    p.c = cell_from(s == 0 ? SWEEP_KIND_PLAIN : kind_b, buf, bytes,
+                    depth, 16, s == 0 ? waves_plain : waves_async,
+                    s == 0 ? La : Lb, opt);
+    p.grid = grid;
+    p.threads = threads;
+    p.lds = lds;
+    p.max_wgs = nb;
+    p.fa = fa;
+    const uint64_t Q = s == 0 ? a.Q_a : a.Q_b;
+    const uint32_t nw = s == 0 ? wa : wb;
+    p.plan.pub.grid_wgs = grid;
+    p.plan.pub.wg_threads = threads;
+    p.plan.pub.waves = nw;
+    p.plan.pub.n_vec = s == 0 ? a.n_vec_a : a.n_vec_b;
+    p.plan.pub.Q = Q;
+    p.plan.pub.issued_loads = 64ull * (uint64_t)depth * Q;
+    p.plan.pub.issued_bytes = p.plan.pub.issued_loads * 16ull;
+    p.plan.pub.iters_min = nw ? (uint32_t)(Q / nw) : 0;
+    p.plan.pub.iters_max = nw ? (uint32_t)((Q + nw - 1) / nw) : 0;
+    const uint64_t Ls = s == 0 ? La : Lb;
+    p.plan.pub.mismatch = Ls ? (double)(Ls - p.plan.pub.issued_loads) / (double)Ls : 0.0;
+    if (on) {
+      fill_result(*d, p, d->res_h[s], ms, &out[s]);
+    } else {
+      std::memset(&out[s], 0, sizeof(out[s]));
+    }
+  }
+  return SWEEP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -557,98 +666,15 @@ int sweep_two_stream(const void* buf, size_t bytes, int depth, int waves_plain,
 int sweep_two_stream_kind(const void* buf, size_t bytes, int depth, int waves_plain,
                           int waves_async, int kind_b, uint64_t total_logical_loads,
                           const sweep_opts_t* opt, sweep_result_t out[2]) {
-  if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
-  if (kind_b != SWEEP_KIND_PLAIN && kind_b != SWEEP_KIND_LDS_ASYNC)
-    return fail(SWEEP_EINVAL, "stream B runs plain loads or the LDS-direct ring");
-  const bool b_plain = kind_b == SWEEP_KIND_PLAIN;
-  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
-  if (depth < 1 || depth > 16) return fail(SWEEP_EINVAL, "depth must be in 1..16");
-  if (waves_plain < 0 || waves_plain > 8 || waves_async < 0 || waves_async > 8 ||
-      waves_plain + waves_async == 0)
-    return fail(SWEEP_EINVAL, "waves_plain and waves_async must be in 0..8, not both 0");
-  if (bytes == 0) return fail(SWEEP_EINVAL, "empty buffer");
-  if (bytes % 2048 || reinterpret_cast<uintptr_t>(buf) % 16)
-    return fail(SWEEP_EALIGN, "two-stream needs a 16-byte aligned buffer, bytes % 2048 == 0");
-  if (total_logical_loads == 0) return fail(SWEEP_EINVAL, "total_logical_loads is 0");
-  const int pol = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
-  if (pol < 0 || pol > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
-  std::lock_guard<std::mutex> lk(g_mu);
-  Dev* d = nullptr;
-  SW_TRY(current_dev(&d));
-  const uint32_t grid = (opt && opt->grid_wgs) ? opt->grid_wgs : d->num_cus;
-  const uint64_t n_vec = bytes / 16, half = n_vec / 2;
-  const uint64_t La = total_logical_loads / 2, Lb = total_logical_loads - La;
-  TwoStreamArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.buf_a = static_cast<const uint8_t*>(buf);
-  a.n_vec_a = half;
-  a.buf_b = static_cast<const uint8_t*>(buf) + half * 16;
-  a.n_vec_b = n_vec - half;
-  a.waves_a = (uint32_t)waves_plain;
-  a.waves_b = (uint32_t)waves_async;
-  a.b_plain = b_plain ? 1u : 0u;
-  if (waves_plain) region_plan(a.n_vec_a, depth, La, grid * a.waves_a, &a.Q_a, &a.stride_a);
-  if (waves_async) region_plan(a.n_vec_b, depth, Lb, grid * a.waves_b, &a.Q_b, &a.stride_b);
-  if ((waves_plain && a.Q_a == 0) || (waves_async && a.Q_b == 0))
-    return fail(SWEEP_EINVAL, "L is smaller than one wave-group per stream");
-  const uint32_t threads = (uint32_t)(waves_plain + waves_async) * 64u;
-  const uint32_t ring = b_plain ? 0u : (uint32_t)waves_async * (uint32_t)depth * 1024u;
-  if (ring > d->lds_per_wg_max) return fail(SWEEP_EOCCUPANCY, "LDS ring exceeds the per-workgroup LDS");
-  size_t lds = ring;
-  if (pin_of(opt)) lds = std::max<size_t>(lds, pin_padding(1, ring, d->lds_per_cu, d->lds_per_wg_max));
-  const void* fn = two_stream_kernel(depth, pol);
-  if (!fn) return fail(SWEEP_EINVAL, "no two-stream kernel for this depth and policy");
-  hipFuncAttributes fa;
-  HIP_TRY(hipFuncGetAttributes(&fa, fn));
-  int nb = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds));
-  if (nb < 1) return fail(SWEEP_EOCCUPANCY, "two-stream workgroup does not fit a CU");
-  const uint32_t wa = grid * a.waves_a, wb = grid * a.waves_b;
-  SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)wa + wb));
-  SW_TRY(ensure_events(*d, 3));
-  sweep_wave_rec_t* rec = (opt && opt->wave_out) ? opt->wave_out : d->rec;
-  a.rec = rec;
-  a.lane_out = opt ? opt->lane_out : nullptr;
-  hipStream_t st = as_stream(opt);
-  SW_TRY(upload_offsets(*d, {0ull, (uint64_t)wa, (uint64_t)wa + wb}, st));
-  HIP_TRY(launch_timed(fn, grid, threads, lds, st, a, d->ev[0], d->ev[1]));
-  HIP_TRY(launch_finish_cells(rec, d->offs, 2, d->res, st));
-  HIP_TRY(hipMemcpyAsync(d->res_h, d->res, 2 * sizeof(CellRes), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipEventRecord(d->ev[2], st));
-  HIP_TRY(hipEventSynchronize(d->ev[2]));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
-  for (int s = 0; s < 2; ++s) {
-    const bool on = s == 0 ? waves_plain > 0 : waves_async > 0;
-    Prepared p;
-    p.c = cell_from(s == 0 ? SWEEP_KIND_PLAIN : kind_b, buf, bytes,
-                    depth, 16, s == 0 ? waves_plain : waves_async,
-                    s == 0 ? La : Lb, opt);
-    p.grid = grid;
-    p.threads = threads;
-    p.lds = lds;
-    p.max_wgs = nb;
-    p.fa = fa;
-    const uint64_t Q = s == 0 ? a.Q_a : a.Q_b;
-    const uint32_t nw = s == 0 ? wa : wb;
-    p.plan.pub.grid_wgs = grid;
-    p.plan.pub.wg_threads = threads;
-    p.plan.pub.waves = nw;
-    p.plan.pub.n_vec = s == 0 ? a.n_vec_a : a.n_vec_b;
-    p.plan.pub.Q = Q;
-    p.plan.pub.issued_loads = 64ull * (uint64_t)depth * Q;
-    p.plan.pub.issued_bytes = p.plan.pub.issued_loads * 16ull;
-    p.plan.pub.iters_min = nw ? (uint32_t)(Q / nw) : 0;
-    p.plan.pub.iters_max = nw ? (uint32_t)((Q + nw - 1) / nw) : 0;
-    const uint64_t Ls = s == 0 ? La : Lb;
-    p.plan.pub.mismatch = Ls ? (double)(Ls - p.plan.pub.issued_loads) / (double)Ls : 0.0;
-    if (on) {
-      fill_result(*d, p, d->res_h[s], ms, &out[s]);
-    } else {
-      std::memset(&out[s], 0, sizeof(out[s]));
-    }
-  }
-  return SWEEP_OK;
+  return two_stream_impl(buf, bytes, depth, waves_plain, waves_async, kind_b,
+                         total_logical_loads, false, opt, out);
+}
+
+int sweep_two_stream_split(const void* buf, size_t bytes, int depth, int waves_a,
+                           int waves_b, int kind_b, uint64_t total_logical_loads,
+                           const sweep_opts_t* opt, sweep_result_t out[2]) {
+  return two_stream_impl(buf, bytes, depth, waves_a, waves_b, kind_b,
+                         total_logical_loads, true, opt, out);
 }
 
 int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,

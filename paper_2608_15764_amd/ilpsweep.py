@@ -125,6 +125,9 @@ _SIG = {
     "sweep_two_stream_kind": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
                                         C.c_int, C.c_uint64, C.POINTER(sweep_opts_t),
                                         C.POINTER(sweep_result_t)]),
+    "sweep_two_stream_split": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                         C.c_int, C.c_uint64, C.POINTER(sweep_opts_t),
+                                         C.POINTER(sweep_result_t)]),
     "sweep_run": (C.c_int, [C.POINTER(sweep_cell_t), C.c_int,
                             C.POINTER(sweep_opts_t), C.POINTER(sweep_result_t)]),
     "sweep_batched": (C.c_int, [C.POINTER(sweep_cell_t), C.c_int,
@@ -293,6 +296,16 @@ def sweep_two_stream_kind(buf, bytes_, depth, waves_a, waves_b, kind_b,
     _check(lib.sweep_two_stream_kind(_ptr(buf), bytes_, depth, waves_a, waves_b,
                                      kind_b, total_logical_loads, C.byref(o), r),
            "sweep_two_stream_kind")
+    return r[0].as_dict(), r[1].as_dict()
+
+
+def sweep_two_stream_split(buf, bytes_, depth, waves_a, waves_b, kind_b,
+                           total_logical_loads, opts=None):
+    r = (sweep_result_t * 2)()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_two_stream_split(_ptr(buf), bytes_, depth, waves_a, waves_b,
+                                      kind_b, total_logical_loads, C.byref(o), r),
+           "sweep_two_stream_split")
     return r[0].as_dict(), r[1].as_dict()
 
 

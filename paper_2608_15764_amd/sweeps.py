@@ -283,18 +283,21 @@ def path_comparison(buf, nbytes, L, depths=range(1, 17), waves_list=(1, 2, 4, 8)
 
 
 def two_stream(buf, nbytes, L, depths=(4, 8), pairs=((4, 4),), n=3,
-               policy=isw.CACHE_DEFAULT, kind_b=isw.KIND_LDS_ASYNC):
+               policy=isw.CACHE_DEFAULT, kind_b=isw.KIND_LDS_ASYNC, split=False):
     """Displacement of each stream by the other (Section 4.4): for every
     depth and (stream-A waves, stream-B waves) pair per workgroup, the
     co-resident bandwidth of each stream against the same stream solo.
     Stream A runs plain loads; stream B the LDS-direct ring (``kind_b =
     KIND_LDS_ASYNC``, cross-mechanism) or plain loads too (``KIND_PLAIN``,
-    the section's same-mechanism measurement)."""
+    the section's same-mechanism measurement).  With ``split`` the streams
+    run on different CUs (sweep_two_stream_split), and the solo runs keep
+    that placement."""
     opts = isw.make_opts(cache_policy=policy)
+    call = isw.sweep_two_stream_split if split else isw.sweep_two_stream_kind
     out = {}
 
     def run(D, wa, wb):
-        return isw.sweep_two_stream_kind(buf, nbytes, D, wa, wb, kind_b, L, opts)
+        return call(buf, nbytes, D, wa, wb, kind_b, L, opts)
 
     for D in depths:
         for wa, wb in pairs:

@@ -190,6 +190,73 @@ def test_two_stream_matches_oracle(D, wa, wb, kind_b):
         assert (res["sum32"], res["xor32"]) == checksums.combine(ws, wx)
 
 
+@pytest.mark.parametrize("kind_b", ["lds_async", "plain"])
+@pytest.mark.parametrize("D,wa,wb", [(4, 8, 8), (3, 2, 5), (5, 4, 0), (2, 0, 3), (16, 16, 1)])
+def test_two_stream_split_matches_oracle(D, wa, wb, kind_b):
+    """Split placement: stream A on half of the workgroups, stream B on the
+    other half; per-lane sinks of both streams against the oracle with each
+    stream's own wave count, and the global sinks equal to the same-workgroup
+    run's (the sinks do not depend on which waves read the groups)."""
+    grid = 32
+    n_vec = 64 * 128
+    nbytes = n_vec * 16
+    buf = synth.random_bytes(nbytes, seed=7 + D + 10 * wa + 100 * wb, device="cuda")
+    L = 2 * 64 * D * 300 + 64                  # 300 groups per stream: wraps its half
+    na, nb = grid // 2 * wa, grid // 2 * wb
+    ro = recs(na + nb)
+    lo = lanes((na + nb) * 64)
+    opts = isw.make_opts(grid_wgs=grid, wave_out=ro, lane_out=lo)
+    kb = isw.KIND_LDS_ASYNC if kind_b == "lds_async" else isw.KIND_PLAIN
+    ra, rb = isw.sweep_two_stream_split(buf, nbytes, D, wa, wb, kb, L, opts)
+    words = host_words(buf)
+    (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
+    gs, gx = decode_lanes(lo, na + nb)
+    La, Lb = L // 2, L - L // 2
+    for (base, nv, Ls, nw, off, res) in ((a0, an, La, na, 0, ra),
+                                         (b0, bn, Lb, nb, na, rb)):
+        if nw == 0:
+            assert res["issued_loads"] == 0
+            continue
+        p = oplan.wave_group(Ls, D, nw)
+        assert res["issued_loads"] == p["issued"] and res["waves"] == nw
+        ws, wx = checksums.per_lane(words, 16, D, p["Q"], nw, base=base, n_vec=nv)
+        assert np.array_equal(gs[off:off + nw], ws)
+        assert np.array_equal(gx[off:off + nw], wx)
+        assert (res["sum32"], res["xor32"]) == checksums.combine(ws, wx)
+    sa, sb = isw.sweep_two_stream_kind(buf, nbytes, D, min(wa, 8), min(wb, 8), kb, L,
+                                       isw.make_opts(grid_wgs=grid))
+    for same, split_ in ((sa, ra), (sb, rb)):
+        if split_["issued_loads"]:
+            assert (same["sum32"], same["xor32"]) == (split_["sum32"], split_["xor32"])
+
+
+def test_two_stream_split_places_streams_on_different_cus():
+    """At one workgroup per CU the two streams share no CU, and every XCD
+    holds as many CUs of each stream (from the waves' HW_ID / XCC_ID)."""
+    info = isw.sweep_device_info()
+    nbytes = 64 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED + 5)
+    n_wg = info["num_cus"] // 2
+    for kb in (isw.KIND_PLAIN, isw.KIND_LDS_ASYNC):
+        na, nb = n_wg * 8, n_wg * 4
+        ro = recs(na + nb)
+        isw.sweep_two_stream_split(buf, nbytes, 4, 8, 4, kb, nbytes // 16,
+                                   isw.make_opts(wave_out=ro))
+        rr = decode_recs(ro)
+        hw = rr["hw_id"].astype(np.int64)
+        xcc = rr["xcc_id"].astype(np.int64) & 0xF
+        cu = xcc << 16 | ((hw >> 8) & 0xFF)
+        cus_a, cus_b = set(cu[:na].tolist()), set(cu[na:].tolist())
+        print(f"kind_b={kb}: {len(cus_a)} CUs run A, {len(cus_b)} run B, "
+              f"{len(cus_a & cus_b)} both")
+        assert not cus_a & cus_b
+        assert len(cus_a) == len(cus_b) == n_wg
+        per_xcd_a = np.bincount(xcc[:na], minlength=8) // 8
+        per_xcd_b = np.bincount(xcc[na:], minlength=8) // 4
+        assert np.array_equal(per_xcd_a, per_xcd_b)
+
+
 def test_run_and_batched_equal_single_calls():
     nbytes = 4 << 20
     buf = dev_bytes(nbytes)
@@ -316,6 +383,11 @@ def test_host_validation_errors():
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_two_stream_kind(buf, 1 << 20, 4, 2, 2, isw.KIND_LDS_MATCHED, 1 << 16)
     assert e.value.code == isw.EINVAL
+    for wa, wb, grid in ((4, 4, 24), (17, 4, 16), (0, 0, 16)):
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_two_stream_split(buf, 1 << 20, 4, wa, wb, isw.KIND_PLAIN, 1 << 16,
+                                       isw.make_opts(grid_wgs=grid))
+        assert e.value.code == isw.EINVAL
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_reduce_fp(buf, 10, 9)
     assert e.value.code == isw.EINVAL
@@ -433,6 +505,9 @@ def test_sweep_drivers_run_small():
     tp = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((2, 2),), n=1,
                            kind_b=isw.KIND_PLAIN)
     assert tp["D4_A2_B2"]["co_b_gbps"] > 0
+    tsp = sweeps.two_stream(buf, nbytes, nbytes // 16, depths=(4,), pairs=((4, 2),), n=1,
+                            kind_b=isw.KIND_PLAIN, split=True)
+    assert tsp["D4_A4_B2"]["co_a_gbps"] > 0 and tsp["D4_A4_B2"]["solo_b_gbps"] > 0
     al = sweeps.allocation_sweep([1 << 20, 4 << 20], Ks=(1, 2), waves_list=(8,), L=1 << 20, n=1)
     assert all(v["checksums_consistent"] for v in al.values())
     of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
