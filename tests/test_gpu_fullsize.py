@@ -245,13 +245,19 @@ def test_lds_paths_full_size(c4, kind, D, W):
         assert (rr["sum32"][wave], rr["xor32"][wave]) == want
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("kind_b", [isw.KIND_LDS_ASYNC, isw.KIND_PLAIN])
 @pytest.mark.parametrize("D", [4, 8])
-def test_two_stream_full_size(c4, D, kind_b):
+def test_two_stream_full_size(c4, D, kind_b, split):
+    """The bench's two-stream launches (4 + 4 waves in one workgroup, or
+    8 + 8 on different CUs): each stream's sinks are its whole half."""
     buf, nbytes, _seed, words = c4
     n_vec = nbytes // 16
     (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
-    ra, rb = isw.sweep_two_stream_kind(buf, nbytes, D, 4, 4, kind_b, n_vec)
+    if split:
+        ra, rb = isw.sweep_two_stream_split(buf, nbytes, D, 8, 8, kind_b, n_vec)
+    else:
+        ra, rb = isw.sweep_two_stream_kind(buf, nbytes, D, 4, 4, kind_b, n_vec)
     assert (ra["sum32"], ra["xor32"]) == checksums.whole_buffer(words[a0 * 4:(a0 + an) * 4])
     assert (rb["sum32"], rb["xor32"]) == checksums.whole_buffer(words[b0 * 4:(b0 + bn) * 4])
     assert ra["issued_loads"] + rb["issued_loads"] == n_vec
