@@ -416,11 +416,15 @@ def main():
             pcells, pmeta, _ = sweeps.drop_infeasible(pcells, pmeta)
             s2 = sweeps.summarize_k_sweep(pmeta, [isw.sweep_run(pcells)])
             c16 = s2["curves"].get(16, {})
+            c4 = s2["curves"].get(4, {})
             pc[name] = {"peak_gbps": round(s2["peak_gbps"], 1),
                         "best_waves_per_cu": s2["best_waves_per_cu"],
                         "paper_like_decline_2_8": c16.get("decline_2_8"),
                         "paper_like_median_gbps": {k: round(v, 1) for k, v in
-                                                   c16.get("median_gbps", {}).items()}}
+                                                   c16.get("median_gbps", {}).items()},
+                        # one wave per SIMD, the lowest occupancy of the sweep
+                        "one_wave_per_simd_gbps": {k: round(v, 1) for k, v in
+                                                   c4.get("median_gbps", {}).items()}}
         result["policy_curves"] = pc
         result["baseline_fixed_iterations"] = sweeps.fixed_iteration_arm(buf, nbytes)
         result["completion_spread"] = sweeps.completion_spread(
