@@ -66,6 +66,12 @@ int main(int argc, char** argv) {
              (unsigned long long)rs[i].issued_loads);
   }
   CHECK(sweep_graph_destroy(g));
+  /* the two streams on different CUs, over the buffer's two halves */
+  sweep_result_t r2[2];
+  CHECK(sweep_two_stream_split(buf, bytes, 4, 8, 8, SWEEP_KIND_PLAIN, bytes / 16, &opt, r2));
+  for (int i = 0; i < 2; ++i)
+    printf("split_%c %u %u %llu\n", i ? 'b' : 'a', r2[i].sum32, r2[i].xor32,
+           (unsigned long long)r2[i].issued_loads);
   CHECK(sweep_shutdown());
   (void)hipFree(buf);
   return 0;

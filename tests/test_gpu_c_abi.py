@@ -52,3 +52,8 @@ def test_plain_c_program(tmp_path):
     assert res["graph_K2_rep1"] == (*checksums.whole_buffer(words1), L)
     want1 = checksums.combine(*checksums.per_wave(words1, 16, 3, p["Q"], n_waves))
     assert res["graph_K3_rep1"] == (*want1, p["issued"])
+    # split two-stream launch over the refilled buffer: each stream reads
+    # its whole half exactly once
+    (a0, an), (b0, bn) = checksums.two_stream_regions(L)
+    assert res["split_a"] == (*checksums.whole_buffer(words1[a0 * 4:(a0 + an) * 4]), an)
+    assert res["split_b"] == (*checksums.whole_buffer(words1[b0 * 4:(b0 + bn) * 4]), bn)
