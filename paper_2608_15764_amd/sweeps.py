@@ -340,6 +340,9 @@ def size_class(nbytes):
     return len(SIZE_CLASS_EDGES)
 
 
+# Every point must be one whole pass (64 K V divides its size, a multiple of
+# 64 KiB), which holds for the powers of two only: K = 7, next to the
+# sweep's best cells, would leave up to 7 KiB of a point unread.
 DEFAULT_SPACE = {"vec_widths": [16, 8], "Ks": [1, 2, 4, 8, 16],
                  "waves_per_cu": [4, 8, 16, 32],
                  "policies": [isw.CACHE_DEFAULT, isw.CACHE_NT,
