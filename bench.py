@@ -27,8 +27,10 @@ Reported beside it:
                 autotuned graph-batched sweep, precision sums, latency
                 ladder, order/footprint and regime map (--no-extras skips)
 
-Prints one JSON line.  --gpus N with N > 1 exits: the benchmark measures
-one GPU.
+The full result goes to a JSON file (--json-out); standard output ends
+with one compact JSON line (under 4 KB) holding the headline figures, the
+roofline, the CPU baseline and one summary per extra configuration.
+--gpus N with N > 1 exits: the benchmark measures one GPU.
 """
 import argparse
 import hashlib
@@ -103,7 +105,9 @@ def parse():
                          "tuning, e.g. f32=8,bf16=8,fp8_e4m3=4 (for profiling "
                          "the tuned launches alone)")
     ap.add_argument("--json-out", default=None,
-                    help="also write the full result to this file")
+                    help="file for the full result (default "
+                         "gpurun_out/bench_detail.json); standard output ends "
+                         "with a compact headline line")
     ap.add_argument("--record", default=None,
                     help="append one JSON line per timed launch (raw log) to this file")
     return ap.parse_args()
@@ -173,7 +177,7 @@ def cpu_baseline_multi(seed, nbytes, L, Ks, n_waves, gpu_sinks, issued_bytes):
                       "process); buffer generation excluded"}
 
 
-def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
+def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf, num_cus):
     """Oracle per-wave checksums of one occupancy's whole K curve (one full
     cell per K), timed on the host and checked against the GPU's records."""
     import numpy as np
@@ -185,7 +189,7 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
                    ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
     gpu = {}
     for K in Ks:
-        rec = torch.zeros(256 * waves_per_cu * 32, dtype=torch.uint8, device="cuda")
+        rec = torch.zeros(num_cus * waves_per_cu * 32, dtype=torch.uint8, device="cuda")
         r = isw.sweep_plain(gpu_buf, nbytes, K, 16, waves_per_cu, L,
                             isw.make_opts(wave_out=rec))
         gpu[K] = (r, rec.cpu().numpy().view(dt)[: r["waves"]])
@@ -222,6 +226,89 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf):
     }
 
 
+def timed_graph(isw, cells, steps, warmup):
+    """Capture ``cells`` once as a hipGraph, replay it ``warmup`` times
+    untimed, then ``steps`` times between two device synchronisations.
+    Returns (per-replay result lists, per-replay event ms, wall seconds)."""
+    import torch
+    arr = isw.cell_array(cells)
+    graph = isw.sweep_graph_create(arr)
+    try:
+        for _ in range(warmup):
+            isw.sweep_graph_launch(graph, raw=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [isw.sweep_graph_launch(graph, raw=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        isw.sweep_graph_destroy(graph)
+    return [isw.result_dicts(r) for r, _ in outs], [ms for _, ms in outs], t1 - t0
+
+
+def curve_rows(summ, peak):
+    return {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                "min_gbps": {k: round(v, 1) for k, v in c["min_gbps"].items()},
+                "best_gbps": {k: round(v, 1) for k, v in c["best_gbps"].items()},
+                "pct_of_best_cell": {k: round(100 * v / peak, 1)
+                                     for k, v in c["median_gbps"].items()},
+                "in_flight_mib": {k: v / 2**20 for k, v in c["in_flight_bytes"].items()},
+                "littles_law_latency_ns": {k: round(v, 1) for k, v in
+                                           c["implied_latency_ns"].items()},
+                "peak_K": c["peak_K"], "knee_K": c["knee_K"],
+                "regime": c["regime"], "decline_2_8": c.get("decline_2_8"),
+                "paired_declines_2_8": [round(x, 4) for x in c.get("paired_declines_2_8", [])],
+                "by_order": c["by_order"]}
+            for w, c in summ["curves"].items()}
+
+
+def paper_like(summ, w=16):
+    c = summ["curves"].get(w)
+    if c is None:
+        return None
+    return {"waves_per_cu": w, "median_gbps": c["median_gbps"],
+            "peak_K": c["peak_K"], "decline_2_8": c.get("decline_2_8"),
+            "paired_declines_2_8": sorted(round(x, 4) for x in c.get("paired_declines_2_8", [])),
+            "regime": c["regime"], "by_order": c["by_order"]}
+
+
+def strict_cg_sweep(a, isw, sweeps, stats, buf, nbytes, L, waves_list, Ks):
+    """The same K sweep under the strict analogue of the paper's .cg
+    operator (L1 bypass, no streaming hint), captured as its own graph and
+    replayed with the headline's steps and warm-up (Section 4.2, Table 1
+    primary cell; "Repeatability")."""
+    pol = isw.CACHE_BYPASS_L1
+    cells, meta = sweeps.plain_k_cells(buf, nbytes, L, pol, waves_list, Ks)
+    cells, meta, _ = sweeps.drop_infeasible(cells, meta)
+    runs, ms, wall = timed_graph(isw, cells, a.steps, a.warmup)
+    summ = sweeps.summarize_k_sweep(meta, runs)
+    step_bytes = sum(r["issued_bytes"] for r in runs[0])
+    best_w = summ["best_waves_per_cu"]
+    pl = paper_like(summ)
+    bo = (pl or {}).get("by_order", {})
+    paired = (pl or {}).get("paired_declines_2_8") or []
+    return {
+        "policy": "bypass_l1",
+        "value": round(a.steps * step_bytes / wall / 1e9, 1),
+        "ms_per_step": round(wall / a.steps * 1e3, 3),
+        "curve_peak_gbps": round(summ["peak_gbps"], 1),
+        "curve_peak_frac_of_hbm": round(summ["peak_gbps"] / stats.HBM_PEAK_GBPS, 4),
+        "best_waves_per_cu": best_w,
+        "peak_K_at_best": summ["curves"][best_w]["peak_K"],
+        "paper_like_decline_2_8": None if pl is None else pl["decline_2_8"],
+        "paper_like_decline_2_8_asc": (bo.get("asc") or {}).get("decline_2_8"),
+        "paper_like_decline_2_8_rev": (bo.get("rev") or {}).get("decline_2_8"),
+        "paper_like_paired_decline_median": stats.median(paired) if paired else None,
+        "paper_like_cell": pl,
+        "curves": curve_rows(summ, summ["peak_gbps"]),
+        "kset_mismatch": summ["kset_mismatch"],
+        "checksums_consistent": summ["checksums_consistent"],
+        "residency_flags": summ["residency_flags"],
+        "anomalous_launches": summ["anomalous_launches"],
+        "graph_replay_event_ms_median": round(sorted(ms)[len(ms) // 2], 3),
+    }
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--cpu-oracle-worker":
         return cpu_oracle_worker(sys.argv[2])
@@ -239,7 +326,7 @@ def main():
 
     import torch
     from paper_2608_15764_amd import ilpsweep as isw
-    from paper_2608_15764_amd import stats, sweeps
+    from paper_2608_15764_amd import report, stats, sweeps
 
     from paper_2608_15764_amd import environment
     torch.cuda.set_device(0)
@@ -282,7 +369,10 @@ def main():
         return 0
     if a.only:
         out_extra = run_extras(a, isw, sweeps, only=a.only)
-        print(json.dumps({"only": a.only, "rows": out_extra}, default=str))
+        if a.json_out:
+            report.write_detail({"only": a.only, "rows": out_extra}, a.json_out)
+        print(json.dumps({"only": a.only, "detail": a.json_out,
+                          "rows": sorted(out_extra)}, default=str))
         return 0
 
     nbytes, L = 1 << 30, 1 << 26
@@ -296,25 +386,14 @@ def main():
     # the step is one replay of the sweep captured once as a hipGraph (one
     # kernel node per cell, then the finishing node); each replay is timed
     # with a hipEvent pair on the stream it is launched on
-    arr = isw.cell_array(cells)
-    graph = isw.sweep_graph_create(arr)
-    for _ in range(a.warmup):
-        isw.sweep_graph_launch(graph, raw=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = [isw.sweep_graph_launch(graph, raw=True) for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    isw.sweep_graph_destroy(graph)
-    runs = [isw.result_dicts(r) for r, _ in outs]
-    graph_ms = [ms for _, ms in outs]
+    runs, graph_ms, wall = timed_graph(isw, cells, a.steps, a.warmup)
     if a.record:
         sweeps.write_records(a.record, meta, runs,
                              {"policy": a.policy, "buffer_bytes": nbytes, "L": L})
 
     env_after = environment.sysfs_metrics()
     step_bytes = sum(r["issued_bytes"] for r in runs[0])
-    value = a.steps * step_bytes / (t1 - t0) / 1e9
+    value = a.steps * step_bytes / wall / 1e9
     # average launch duration = replay time / kernels per replay: an upper
     # bound on the mean kernel time (it holds the gaps between graph nodes
     # and the small finishing kernel), so `achieved` is a lower bound
@@ -325,7 +404,6 @@ def main():
     summ = sweeps.summarize_k_sweep(meta, runs)
     best_w = summ["best_waves_per_cu"]
     cb = summ["curves"][best_w]
-    w4 = summ["curves"].get(16)
 
     result = {
         "metric": "attained HBM GB/s vs offered loads/thread K; % of HBM peak; K=2\u21928 decline %",
@@ -334,7 +412,7 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round((t1 - t0) / a.steps * 1e3, 3),
+        "ms_per_step": round(wall / a.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -354,23 +432,8 @@ def main():
         "best_waves_per_cu": best_w,
         "peak_K_at_best": cb["peak_K"],
         "decline_2_8_at_best": cb.get("decline_2_8"),
-        "paper_like_cell": None if w4 is None else {
-            "waves_per_cu": 16, "median_gbps": w4["median_gbps"],
-            "peak_K": w4["peak_K"], "decline_2_8": w4.get("decline_2_8"),
-            "paired_declines_2_8": sorted(round(x, 4) for x in w4.get("paired_declines_2_8", [])),
-            "regime": w4["regime"], "by_order": w4["by_order"]},
-        "curves": {w: {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
-                       "min_gbps": {k: round(v, 1) for k, v in c["min_gbps"].items()},
-                       "best_gbps": {k: round(v, 1) for k, v in c["best_gbps"].items()},
-                       "pct_of_best_cell": {k: round(100 * v / summ["peak_gbps"], 1)
-                                            for k, v in c["median_gbps"].items()},
-                       "in_flight_mib": {k: v / 2**20 for k, v in c["in_flight_bytes"].items()},
-                       "littles_law_latency_ns": {k: round(v, 1) for k, v in
-                                                  c["implied_latency_ns"].items()},
-                       "peak_K": c["peak_K"], "knee_K": c["knee_K"],
-                       "regime": c["regime"], "decline_2_8": c.get("decline_2_8"),
-                       "by_order": c["by_order"]}
-                   for w, c in summ["curves"].items()},
+        "paper_like_cell": paper_like(summ),
+        "curves": curve_rows(summ, summ["peak_gbps"]),
         "kset_mismatch": summ["kset_mismatch"],
         "checksums_consistent": summ["checksums_consistent"],
         "residency_flags": summ["residency_flags"],
@@ -389,9 +452,14 @@ def main():
         "environment": {"static": environment.static_info(),
                         "gpu_before": env_before, "gpu_after": env_after},
     }
+    # the strict .cg analogue, timed like the headline
+    if a.policy != "bypass_l1":
+        result["strict_cg"] = strict_cg_sweep(a, isw, sweeps, stats, buf, nbytes, L,
+                                              waves_list, Ks)
     # the same sweep launched eagerly, cell by cell (sweep_run): the cost of
     # one host launch per kernel against the graph replay timed above, and
     # every kernel's own duration from the events its dispatch stamps
+    arr = isw.cell_array(cells)
     isw.sweep_run(arr, raw=True)
     torch.cuda.synchronize()
     eager = []
@@ -408,8 +476,14 @@ def main():
         "dispatch_event_gbps": round(step_bytes / (disp_ms * 1e6), 1),
         "graph_step_ms": result["ms_per_step"],
         "graph_replay_event_ms": round(sorted(graph_ms)[len(graph_ms) // 2], 3)}
+    lat = None
     if not a.no_extras:
-        # one untimed pass of the same sweep under every cache policy
+        # the unloaded HBM round trip, then where the sweep's distance from
+        # the datasheet goes (ceilings by design, tail loss, residual)
+        lat = sweeps.hbm_latency_ns()
+        result["gap"] = sweeps.gap_breakdown(buf, nbytes, L, policy, summ, lat,
+                                             waves_list, Ks)
+        # one untimed pass of the same sweep under the other cache policies
         pc = {}
         for name, pol in isw.POLICY_NAMES.items():
             pcells, pmeta = sweeps.plain_k_cells(buf, nbytes, L, pol, waves_list, Ks)
@@ -429,18 +503,19 @@ def main():
         result["baseline_fixed_iterations"] = sweeps.fixed_iteration_arm(buf, nbytes)
         result["completion_spread"] = sweeps.completion_spread(
             buf, nbytes, L, isw.POLICY_NAMES[a.policy], waves_list, K=4)
-        result["streaming_gate"] = sweeps.streaming_gate(buf, nbytes)
+        result["streaming_gate"] = sweeps.streaming_gate(buf, nbytes, latency_ns=lat)
+        # the same gate form with 16-byte loads: four times the bytes in flight
+        result["streaming_gate_16B"] = sweeps.streaming_gate(buf, nbytes, vec_width=16,
+                                                             latency_ns=lat)
     if not a.no_cpu_baseline:
         ks_best = sorted({m["K"] for m in meta if m["waves_per_cu"] == best_w})
-        result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf)
+        result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf,
+                                              info["num_cus"])
     del buf
     if not a.no_extras:
         result["rows"] = run_extras(a, isw, sweeps, best_w=best_w)
-    line = json.dumps(result, default=str)
-    if a.json_out:
-        with open(a.json_out, "w") as f:
-            f.write(line + "\n")
-    print(line, flush=True)
+    detail = a.json_out or os.path.join("gpurun_out", "bench_detail.json")
+    report.emit(result, detail, sys.stdout)
     return 0
 
 

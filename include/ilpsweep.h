@@ -116,6 +116,11 @@ typedef struct {
   sweep_wave_rec_t* wave_out; /* device, n_waves records, or NULL           */
   uint32_t* lane_out;      /* device, 2 u32 (sum, xor) per thread, or NULL  */
   int       order;         /* SWEEP_ORDER_* (plain kernel)                  */
+  uint64_t  wave_out_cap;  /* records wave_out holds; a call whose launch
+                              has more waves fails with SWEEP_EINVAL and
+                              writes nothing (required with wave_out)       */
+  uint64_t  lane_out_cap;  /* (sum, xor) pairs lane_out holds, i.e. threads;
+                              checked like wave_out_cap                      */
 } sweep_opts_t;
 
 typedef struct {

@@ -355,6 +355,19 @@ sweep_cell_t cell_from(int kind, const void* buf, size_t bytes, int K, int V,
 
 int pin_of(const sweep_opts_t* o) { return o ? o->pin_occupancy : 1; }
 
+// The caller's per-wave and per-lane output buffers must hold a launch of
+// `waves` waves; checked before anything is enqueued.
+int check_outputs(const sweep_opts_t* o, uint64_t waves) {
+  if (!o) return SWEEP_OK;
+  if (o->wave_out && o->wave_out_cap < waves)
+    return fail(SWEEP_EINVAL, "wave_out holds " + std::to_string(o->wave_out_cap) +
+                                  " records, the launch has " + std::to_string(waves) + " waves");
+  if (o->lane_out && o->lane_out_cap < waves * 64ull)
+    return fail(SWEEP_EINVAL, "lane_out holds " + std::to_string(o->lane_out_cap) +
+                                  " lanes, the launch has " + std::to_string(waves * 64ull));
+  return SWEEP_OK;
+}
+
 // Runs prepared cells back to back, each writing its own record region,
 // then one finishing kernel for all cells; one synchronisation at the end.
 int run_prepared(Dev& d, std::vector<Prepared>& ps, hipStream_t st,
@@ -390,6 +403,7 @@ int single_cell(const sweep_cell_t& c, const sweep_opts_t* opt, sweep_result_t* 
   SW_TRY(current_dev(&d));
   std::vector<Prepared> ps(1);
   SW_TRY(prepare(*d, c, pin_of(opt), &ps[0]));
+  SW_TRY(check_outputs(opt, ps[0].plan.pub.waves));
   sweep_result_t r;
   SW_TRY(run_prepared(*d, ps, as_stream(opt), opt ? opt->wave_out : nullptr,
                       opt ? opt->lane_out : nullptr, &r));
@@ -459,6 +473,7 @@ int two_stream_impl(const void* buf, size_t bytes, int depth, int waves_plain,
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, lds));
   if (nb < 1) return fail(SWEEP_EOCCUPANCY, "two-stream workgroup does not fit a CU");
   const uint32_t wa = wg_a * a.waves_a, wb = wg_b * a.waves_b;
+  SW_TRY(check_outputs(opt, (uint64_t)wa + wb));
   SW_TRY(ensure_dev(d->rec, d->rec_cap, (size_t)wa + wb));
   SW_TRY(ensure_events(*d, 3));
   sweep_wave_rec_t* rec = (opt && opt->wave_out) ? opt->wave_out : d->rec;

@@ -35,7 +35,8 @@ class sweep_opts_t(C.Structure):
                 ("mode", C.c_int), ("fixed_iters", C.c_uint32),
                 ("grid_wgs", C.c_uint32), ("pin_occupancy", C.c_int),
                 ("wave_out", C.c_void_p), ("lane_out", C.c_void_p),
-                ("order", C.c_int)]
+                ("order", C.c_int), ("wave_out_cap", C.c_uint64),
+                ("lane_out_cap", C.c_uint64)]
 
 
 class sweep_result_t(C.Structure):
@@ -200,9 +201,32 @@ def _stream(s):
     return int(s)
 
 
+def _nbytes(x):
+    """Size in bytes of a tensor-like buffer, or None for a raw pointer."""
+    if hasattr(x, "numel") and hasattr(x, "element_size"):
+        return x.numel() * x.element_size()
+    return None
+
+
+def _cap(buf, cap, item_bytes, name):
+    """Capacity in items of an output buffer: from the tensor's size, or the
+    caller's ``cap`` for a raw pointer (required then)."""
+    if buf is None:
+        return 0
+    if cap is not None:
+        return int(cap)
+    n = _nbytes(buf)
+    if n is None:
+        raise ValueError(f"{name} is a raw pointer: give {name}_cap")
+    return n // item_bytes
+
+
 def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
               fixed_iters=0, grid_wgs=0, pin_occupancy=True, wave_out=None,
-              lane_out=None, order=ORDER_ROUND_ROBIN):
+              lane_out=None, order=ORDER_ROUND_ROBIN, wave_out_cap=None,
+              lane_out_cap=None):
+    """Options block.  ``wave_out`` / ``lane_out`` capacities (records of 32
+    bytes / lanes of 8 bytes) are taken from the tensors' sizes unless given."""
     o = sweep_opts_t()
     o.stream = _stream(stream)
     o.cache_policy = cache_policy
@@ -213,6 +237,8 @@ def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
     o.wave_out = _ptr(wave_out)
     o.lane_out = _ptr(lane_out)
     o.order = order
+    o.wave_out_cap = _cap(wave_out, wave_out_cap, C.sizeof(sweep_wave_rec_t), "wave_out")
+    o.lane_out_cap = _cap(lane_out, lane_out_cap, 8, "lane_out")
     return o
 
 

@@ -1,0 +1,188 @@
+"""The benchmark's result line.
+
+A benchmark run produces a large result (every curve, every extra
+configuration).  That detail goes to a JSON file; standard output ends with
+one compact JSON object that carries the headline figures: the metric and
+its value, the step time, the roofline of the dominant kernel, the CPU
+baseline and one summary figure per extra configuration.  The compact line
+is bounded in size so that a reader keeping only the tail of the output
+still has all of it.
+
+Bandwidth throughout is issued logical bytes per calibrated nanosecond, in
+decimal GB/s (Section 3, "Timing, residency, statistics").
+"""
+import json
+import os
+
+LINE_LIMIT = 4000          # bytes of the compact line, newline excluded
+
+# Keys the compact line always carries.
+REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+            "roofline", "cpu_baseline")
+
+# Optional sections, dropped last-first if the line would exceed the limit.
+OPTIONAL = ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
+            "peak_K_at_best", "decline_2_8_at_best", "paper_like", "strict_cg",
+            "gap", "eager", "c5a", "c5b", "streaming_gate", "detail")
+
+
+def _r(x, nd=4):
+    if isinstance(x, float):
+        return round(x, nd)
+    return x
+
+
+def _pick(d, keys, nd=4):
+    if not isinstance(d, dict):
+        return None
+    return {k: _r(d[k], nd) for k in keys if k in d}
+
+
+def _config(cfg):
+    c = dict(cfg or {})
+    out = {"workload": c.get("workload")}
+    for k in ("buffer_bytes", "vec_width", "L", "cache_policy", "cells_per_step"):
+        if k in c:
+            out[k] = c[k]
+    ks = c.get("Ks")
+    if ks:
+        out["Ks"] = f"{min(ks)}..{max(ks)}"
+    ws = c.get("waves_per_cu")
+    if ws:
+        out["waves_per_cu"] = f"{min(ws)}..{max(ws)} step {ws[1] - ws[0]}" if len(ws) > 1 else ws[0]
+    if c.get("orders"):
+        out["orders"] = c["orders"]
+    if c.get("infeasible_cells") is not None:
+        out["infeasible_cells"] = len(c["infeasible_cells"])
+    return out
+
+
+def _cpu(cb):
+    if not isinstance(cb, dict):
+        return None
+    out = _pick(cb, ("value", "unit", "cores", "kind", "sample", "host_cpu",
+                     "matches_gpu", "checksum_s", "error"), 3)
+    mp = cb.get("multi_process")
+    if isinstance(mp, dict):
+        out["multi_process"] = _pick(mp, ("value", "cores", "matches_gpu", "error"), 3)
+    return out
+
+
+def _c5a(row):
+    if not isinstance(row, dict):
+        return None
+    return _pick(row, ("batched_aggregate_gbps", "batched_aggregate_frac",
+                       "hbm_aggregate_gbps", "hbm_aggregate_frac",
+                       "batched_best_point_gbps", "plain_aggregate_gbps",
+                       "matches_oracle", "points_checked", "sizes"), 4)
+
+
+def _c5b(row):
+    if not isinstance(row, dict):
+        return None
+    out = {}
+    for kind, v in row.items():
+        if isinstance(v, dict) and "median_gbps" in v:
+            out[kind] = {"gbps": _r(v.get("median_gbps"), 1),
+                         "frac": _r(v.get("frac_of_hbm_peak"), 4),
+                         "abs_err": v.get("abs_err"), "rel_err": v.get("rel_err"),
+                         "within_bound": v.get("within_bound")}
+    return out or None
+
+
+def compact(result, detail_path=None):
+    """The compact headline dict of a full benchmark result."""
+    r = result
+    out = {k: r.get(k) for k in REQUIRED if k not in ("config", "roofline", "cpu_baseline")}
+    out["config"] = _config(r.get("config"))
+    rl = r.get("roofline") or {}
+    out["roofline"] = _pick(rl, ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                 "algorithmic_bytes_per_launch", "mean_launch_us",
+                                 "launches", "kernel"), 4)
+    out["cpu_baseline"] = _cpu(r.get("cpu_baseline"))
+    for k in ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
+              "peak_K_at_best", "decline_2_8_at_best"):
+        if k in r:
+            out[k] = _r(r[k])
+    pl = r.get("paper_like_cell")
+    if isinstance(pl, dict):
+        bo = pl.get("by_order") or {}
+        med = pl.get("median_gbps") or {}
+        out["paper_like"] = {
+            "waves_per_cu": pl.get("waves_per_cu"), "peak_K": pl.get("peak_K"),
+            "decline_2_8": _r(pl.get("decline_2_8")),
+            "decline_2_8_asc": _r((bo.get("asc") or {}).get("decline_2_8")),
+            "decline_2_8_rev": _r((bo.get("rev") or {}).get("decline_2_8")),
+            "gbps_K2": _r(med.get(2), 1), "gbps_K8": _r(med.get(8), 1)}
+    cg = r.get("strict_cg")
+    if isinstance(cg, dict):
+        out["strict_cg"] = _pick(cg, ("policy", "value", "ms_per_step", "curve_peak_gbps",
+                                      "curve_peak_frac_of_hbm", "best_waves_per_cu",
+                                      "peak_K_at_best", "paper_like_decline_2_8",
+                                      "paper_like_decline_2_8_asc",
+                                      "paper_like_decline_2_8_rev",
+                                      "paper_like_paired_decline_median"), 4)
+    gap = r.get("gap")
+    if isinstance(gap, dict):
+        out["gap"] = _pick(gap, ("hbm_latency_ns", "ceiling_frac_of_peak",
+                                 "frac_of_ceiling", "tail_loss", "residual_frac",
+                                 "kernel_frac"), 4)
+    ea = r.get("eager_sweep")
+    if isinstance(ea, dict):
+        out["eager"] = _pick(ea, ("step_ms", "aggregate_gbps", "dispatch_event_gbps"), 1)
+    rows = r.get("rows") or {}
+    c5a = _c5a(rows.get("c5a_batched"))
+    if c5a:
+        out["c5a"] = c5a
+    c5b = _c5b(rows.get("c5b_precision"))
+    if c5b:
+        out["c5b"] = c5b
+    sg = r.get("streaming_gate")
+    if isinstance(sg, dict):
+        out["streaming_gate"] = _pick(sg, ("median_gbps", "median_frac",
+                                           "littles_law_ceiling_gbps", "frac_of_ceiling",
+                                           "verdict"), 4)
+    if detail_path:
+        out["detail"] = detail_path
+    return out
+
+
+def headline_line(result, detail_path=None, limit=LINE_LIMIT):
+    """The compact line as text, at most ``limit`` bytes: optional sections
+    are dropped, last first, until it fits; their names are listed under
+    ``"dropped"``."""
+    c = compact(result, detail_path)
+    dropped = []
+    line = json.dumps(c, separators=(",", ":"), default=str)
+    for k in reversed(OPTIONAL):
+        if len(line.encode()) <= limit:
+            break
+        if k in c:
+            del c[k]
+            dropped.append(k)
+            c["dropped"] = dropped
+            line = json.dumps(c, separators=(",", ":"), default=str)
+    if len(line.encode()) > limit:
+        raise ValueError(f"headline line of {len(line)} bytes exceeds {limit}")
+    return line
+
+
+def write_detail(result, path):
+    """Write the full result as JSON to ``path`` (directories created)."""
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(result, f, default=str)
+        f.write("\n")
+
+
+def emit(result, detail_path, out):
+    """Write the detail file, then print the compact line as the last line
+    of ``out``."""
+    if detail_path:
+        write_detail(result, detail_path)
+    line = headline_line(result, detail_path)
+    out.write(line + "\n")
+    out.flush()
+    return line

@@ -154,6 +154,56 @@ def front_duplicates(blocked, K, n_waves, Q, n_vec, max_iters=64):
     return dup / total if total else 0.0
 
 
+def tail_loss(t0, t1):
+    """Share of the wave slots left idle inside a launch's window:
+    1 - sum of wave durations / (waves x window), from the per-wave start
+    and end clock readings.  Zero when every wave runs the whole window."""
+    n = len(t0)
+    if n == 0:
+        return 0.0
+    lo, hi = min(t0), max(t1)
+    win = hi - lo
+    if win <= 0:
+        return 0.0
+    busy = sum(b - a for a, b in zip(t0, t1))
+    return 1.0 - busy / (n * win)
+
+
+def littles_ceiling_gbps(in_flight, latency_ns, peak_gbps=HBM_PEAK_GBPS):
+    """Little's-law ceiling of a cell: the smaller of the datasheet figure
+    and bytes in flight over the round-trip latency (bytes/ns = GB/s)."""
+    if latency_ns <= 0:
+        raise ValueError("latency must be positive")
+    return min(peak_gbps, in_flight / latency_ns)
+
+
+def gap_split(cells, peak_gbps=HBM_PEAK_GBPS):
+    """Where a sweep's distance from the datasheet figure goes.
+
+    ``cells``: dicts with the cell's issued ``bytes``, its measured ``gbps``,
+    its Little's-law ``ceiling_gbps`` and its ``tail_loss``.  Times are
+    summed over the cells (each cell's bytes at its own rate), so
+
+        kernel_frac = ceiling_frac_of_peak * (1 - tail_loss) * residual_frac
+
+    where ceiling_frac_of_peak is the time at the datasheet rate over the
+    time at every cell's ceiling (what offering too few bytes in flight
+    costs by design), tail_loss is the time-weighted idle share of the wave
+    slots, and residual_frac is what is left unexplained."""
+    if not cells:
+        raise ValueError("no cells")
+    t_meas = sum(c["bytes"] / c["gbps"] for c in cells)
+    t_ceil = sum(c["bytes"] / c["ceiling_gbps"] for c in cells)
+    t_peak = sum(c["bytes"] / peak_gbps for c in cells)
+    tail = sum(c["bytes"] / c["gbps"] * c["tail_loss"] for c in cells) / t_meas
+    kernel = t_peak / t_meas
+    ceil_frac = t_peak / t_ceil
+    of_ceiling = t_ceil / t_meas
+    return {"kernel_frac": kernel, "ceiling_frac_of_peak": ceil_frac,
+            "frac_of_ceiling": of_ceiling, "tail_loss": tail,
+            "residual_frac": of_ceiling / (1.0 - tail) if tail < 1 else None}
+
+
 def summarize_curve(samples):
     """Summary of one response curve {K: [GB/s per launch]}."""
     med = per_k_medians(samples)

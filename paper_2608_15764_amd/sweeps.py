@@ -76,7 +76,8 @@ def plain_k_cells(buf, nbytes, L, policy, waves_list, Ks, orders=("asc", "rev"),
                 c = isw.make_cell(buf, nbytes, K, vec_width, w, L,
                                   cache_policy=policy)
                 cells.append(c)
-                meta.append({"waves_per_cu": w, "order": order, "K": K})
+                meta.append({"waves_per_cu": w, "order": order, "K": K,
+                             "bytes": nbytes})
     return cells, meta
 
 
@@ -96,7 +97,13 @@ def drop_infeasible(cells, meta):
 
 
 def summarize_k_sweep(meta, runs, vec_width=16):
-    """Summary of repeated K-sweep passes (``runs``: list of result lists)."""
+    """Summary of repeated K-sweep passes (``runs``: list of result lists).
+    Every ``meta`` entry names its cell's allocation (``bytes``), which the
+    residency screen needs: a cache-resident buffer may be read faster than
+    HBM allows however many bytes a launch issues over it."""
+    missing = [m for m in meta if "bytes" not in m]
+    if missing:
+        raise ValueError("cell metadata must carry the allocation size 'bytes'")
     by = {}
     checks = {}
     for results in runs:
@@ -142,7 +149,8 @@ def summarize_k_sweep(meta, runs, vec_width=16):
                   dict(zip(("waves_per_cu", "K", "gbps", "ratio"),
                            min(anom, key=lambda a: a[3]))))}
     out["residency_flags"] = sum(
-        stats.residency_flag(r["gbps"], r["issued_bytes"]) for res in runs for r in res)
+        stats.residency_flag(r["gbps"], m["bytes"]) for res in runs
+        for m, r in zip(meta, res))
     best_w = max(out["curves"], key=lambda w: max(out["curves"][w]["median_gbps"].values()))
     out["best_waves_per_cu"] = best_w
     out["peak_gbps"] = max(out["curves"][best_w]["median_gbps"].values())
@@ -538,7 +546,8 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
                 for K in ks:
                     cells.append(isw.make_cell(buf, size, K, 16, waves_per_cu, L,
                                                cache_policy=policy, order=order))
-                    meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K})
+                    meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K,
+                                 "bytes": size})
             arr = isw.cell_array(cells)
             isw.sweep_run(arr, raw=True)
             runs = [isw.sweep_run(arr) for _ in range(n)]
@@ -677,7 +686,8 @@ def fixed_iteration_arm(buf, nbytes, Ks=(1, 2, 4, 8), waves_per_cu=16, iters=Non
             cells.append(isw.make_cell(buf, nbytes, K, 16, waves_per_cu, 0,
                                        cache_policy=policy, mode=isw.FIXED_ITERS,
                                        fixed_iters=iters))
-            meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K})
+            meta.append({"waves_per_cu": waves_per_cu, "order": direction, "K": K,
+                         "bytes": nbytes})
     arr = isw.cell_array(cells)
     isw.sweep_run(arr, raw=True)
     runs = [isw.sweep_run(arr) for _ in range(n)]
@@ -690,21 +700,108 @@ def fixed_iteration_arm(buf, nbytes, Ks=(1, 2, 4, 8), waves_per_cu=16, iters=Non
 
 
 def streaming_gate(buf, nbytes, vec_width=4, K=1, waves_per_cu=32, launches=31,
-                   policy=isw.CACHE_BYPASS_L1_NT):
+                   policy=isw.CACHE_BYPASS_L1_NT, latency_ns=None, pass_frac=0.85):
     """The streaming-read ceiling row of Section 4.1 ("read, 4 B width, ILP
     1"): median and best of ``launches`` one-pass launches, as a fraction
-    of the HBM datasheet figure."""
+    of the HBM datasheet figure.
+
+    With ``latency_ns`` (the unloaded HBM round trip) the row also carries
+    its Little's-law ceiling, min(datasheet, bytes in flight / latency),
+    and a verdict: "pass" if the median reaches ``pass_frac`` of the
+    datasheet; "latency-bound" if the form offers too few bytes in flight
+    for the datasheet (ceiling below ``pass_frac`` of it), so that it cannot
+    pass on this part whatever the memory system does; "fail" otherwise."""
     c = isw.make_cell(buf, nbytes, K, vec_width, waves_per_cu, nbytes // vec_width,
                       cache_policy=policy)
     arr = isw.cell_array([c] * (launches + 1))
     res = isw.sweep_run(arr)[1:]
     g = sorted(r["gbps"] for r in res)
     med = stats.median(g)
-    return {"vec_width": vec_width, "K": K, "waves_per_cu": waves_per_cu,
-            "launches": launches, "median_gbps": round(med, 1),
-            "best_gbps": round(g[-1], 1),
-            "median_frac": med / stats.HBM_PEAK_GBPS,
-            "best_frac": g[-1] / stats.HBM_PEAK_GBPS}
+    out = {"vec_width": vec_width, "K": K, "waves_per_cu": waves_per_cu,
+           "launches": launches, "median_gbps": round(med, 1),
+           "best_gbps": round(g[-1], 1),
+           "median_frac": med / stats.HBM_PEAK_GBPS,
+           "best_frac": g[-1] / stats.HBM_PEAK_GBPS}
+    if latency_ns:
+        fl = stats.in_flight_bytes(res[0]["waves"], K, vec_width)
+        ceil = stats.littles_ceiling_gbps(fl, latency_ns)
+        if med >= pass_frac * stats.HBM_PEAK_GBPS:
+            verdict = "pass"
+        elif ceil < pass_frac * stats.HBM_PEAK_GBPS:
+            verdict = "latency-bound"
+        else:
+            verdict = "fail"
+        out.update({"in_flight_bytes": fl, "latency_ns": round(latency_ns, 1),
+                    "littles_law_ceiling_gbps": round(ceil, 1),
+                    "frac_of_ceiling": med / ceil,
+                    "implied_latency_ns": round(stats.implied_latency_ns(fl, med), 1),
+                    "pass_frac": pass_frac, "verdict": verdict})
+    return out
+
+
+def hbm_latency_ns(footprint=GIB, policy=isw.CACHE_BYPASS_L1, seed=SEED_BASE + 8):
+    """Unloaded HBM round trip: the cold pointer-chase mean over one
+    footprint far above the last-level cache (the latency ladder's own
+    method, one rung)."""
+    row = latency_ladder(footprints=[footprint], policies=(policy,), seed=seed)
+    name = {v: k for k, v in isw.POLICY_NAMES.items()}[policy]
+    return row[footprint][name]["mean_ns"]
+
+
+def wave_rec_dtype():
+    """NumPy dtype of the 32-byte per-wave record (sweep_wave_rec_t)."""
+    import numpy as np
+    return np.dtype([("sum32", "<u4"), ("xor32", "<u4"), ("hw_id", "<u4"),
+                     ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
+
+
+def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
+                  vec_width=16):
+    """Split the K sweep's distance from the datasheet figure into the part
+    the design offers (cells whose bytes in flight over the HBM latency fall
+    below the datasheet), the tail loss of the static equal split (wave
+    slots idle inside the window, from one untimed launch per cell with its
+    per-wave clock records) and a residual.  ``summ`` is the timed sweep's
+    summary; its per-cell medians are the measured rates."""
+    dt = wave_rec_dtype()
+    n_cus = isw.sweep_device_info()["num_cus"]
+    rec = torch.zeros(n_cus * max(waves_list) * dt.itemsize, dtype=torch.uint8,
+                      device="cuda")
+    cells, per_w = [], {}
+    for w in waves_list:
+        curve = summ["curves"].get(w)
+        if curve is None:
+            continue
+        rows = {}
+        for K in Ks:
+            g = curve["median_gbps"].get(K)
+            if g is None:
+                continue
+            opts = isw.make_opts(cache_policy=policy, wave_out=rec)
+            r = isw.sweep_plain(buf, nbytes, K, vec_width, w, L, opts)
+            a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
+            tl = stats.tail_loss(a["t0"].astype("int64").tolist(),
+                                 a["t1"].astype("int64").tolist())
+            fl = stats.in_flight_bytes(r["waves"], K, vec_width)
+            ceil = stats.littles_ceiling_gbps(fl, latency_ns)
+            c = {"bytes": r["issued_bytes"], "gbps": g, "ceiling_gbps": ceil,
+                 "tail_loss": tl}
+            cells.append(c)
+            rows[K] = {"gbps": round(g, 1), "ceiling_gbps": round(ceil, 1),
+                       "frac_of_ceiling": round(g / ceil, 4), "tail_loss": round(tl, 4)}
+        if rows:
+            split = stats.gap_split([c for c in cells[-len(rows):]])
+            per_w[w] = {"cells": rows,
+                        "split": {k: (round(v, 4) if isinstance(v, float) else v)
+                                  for k, v in split.items()}}
+    out = stats.gap_split(cells)
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+    out["hbm_latency_ns"] = round(latency_ns, 1)
+    out["by_waves_per_cu"] = per_w
+    out["method"] = ("ceiling = min(8 TB/s, bytes in flight / unloaded HBM latency); "
+                     "tail loss = 1 - sum of wave durations / (waves x window), one "
+                     "untimed launch per cell; times summed over cells")
+    return out
 
 
 def write_records(path, meta, runs, extra=None):

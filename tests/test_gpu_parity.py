@@ -396,6 +396,38 @@ def test_host_validation_errors():
     assert e.value.code == isw.EALIGN
 
 
+def test_output_buffers_too_small_are_rejected():
+    """A wave_out / lane_out smaller than the launch is refused before any
+    kernel runs, and the buffers stay untouched."""
+    nbytes = 1 << 20
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, SEED)
+    grid = 16                                   # 64 waves
+    ro = recs(63)
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plain(buf, nbytes, 2, 16, 4, nbytes // 16,
+                        isw.make_opts(grid_wgs=grid, wave_out=ro))
+    assert e.value.code == isw.EINVAL
+    lo = lanes(64 * 64 - 1)
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plain(buf, nbytes, 2, 16, 4, nbytes // 16,
+                        isw.make_opts(grid_wgs=grid, lane_out=lo))
+    assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_two_stream_kind(buf, nbytes, 4, 4, 4, isw.KIND_PLAIN, nbytes // 16,
+                                  isw.make_opts(grid_wgs=grid, wave_out=recs(127)))
+    assert e.value.code == isw.EINVAL
+    torch.cuda.synchronize()
+    assert not ro.any() and not lo.any()
+    # a raw pointer needs its capacity stated
+    with pytest.raises(ValueError):
+        isw.make_opts(wave_out=ro.data_ptr())
+    # exactly the launch's size is accepted
+    r = isw.sweep_plain(buf, nbytes, 2, 16, 4, nbytes // 16,
+                        isw.make_opts(grid_wgs=grid, wave_out=recs(64), lane_out=lanes(64 * 64)))
+    assert r["waves"] == 64
+
+
 @pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES[:6])
 def test_plain_blocked_order_matches_oracle(V, K, w, grid, n_vec, L):
     nbytes = n_vec * V

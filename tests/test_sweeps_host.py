@@ -18,7 +18,8 @@ def test_size_classes():
 
 
 def test_raw_records_roundtrip(tmp_path):
-    meta = [{"waves_per_cu": 16, "order": "asc", "K": 1}, {"waves_per_cu": 16, "order": "asc", "K": 2}]
+    meta = [{"waves_per_cu": 16, "order": "asc", "K": 1, "bytes": 1 << 30},
+            {"waves_per_cu": 16, "order": "asc", "K": 2, "bytes": 1 << 30}]
     r = {"issued_bytes": 1, "sum32": 2, "xor32": 3, "gbps": 4.0, "window_ns": 5.0,
          "event_ms": 6.0, "waves": 7}
     p = tmp_path / "raw.jsonl"
@@ -32,7 +33,7 @@ def test_summarize_k_sweep_on_synthetic_results():
     meta, runs = [], [[], []]
     for order in ("asc", "rev"):
         for K in ((1, 2, 4, 8) if order == "asc" else (8, 4, 2, 1)):
-            meta.append({"waves_per_cu": 16, "order": order, "K": K})
+            meta.append({"waves_per_cu": 16, "order": order, "K": K, "bytes": 1 << 30})
     base = {1: 5000.0, 2: 7000.0, 4: 7100.0, 8: 7050.0}
     for p in range(2):
         for m in meta:
@@ -50,7 +51,7 @@ def test_summarize_k_sweep_on_synthetic_results():
 
 
 def test_summarize_k_sweep_discloses_a_slow_launch():
-    meta = [{"waves_per_cu": 8, "order": "asc", "K": K} for K in (1, 2, 4)]
+    meta = [{"waves_per_cu": 8, "order": "asc", "K": K, "bytes": 1 << 30} for K in (1, 2, 4)]
     runs = []
     for p in range(5):
         runs.append([{"gbps": (3000.0 if (p == 3 and m["K"] == 2) else 6000.0),
@@ -60,6 +61,34 @@ def test_summarize_k_sweep_discloses_a_slow_launch():
     a = s["anomalous_launches"]
     assert a["count"] == 1 and a["launches"] == 15
     assert a["worst"] == {"waves_per_cu": 8, "K": 2, "gbps": 3000.0, "ratio": 0.5}
+
+
+def _flat_sweep(alloc_bytes, gbps):
+    meta = [{"waves_per_cu": 16, "order": o, "K": K, "bytes": alloc_bytes}
+            for o in ("asc", "rev") for K in (1, 2, 4, 8)]
+    runs = [[{"gbps": gbps, "issued_loads": 1 << 26, "issued_bytes": 1 << 30,
+              "sum32": 1, "xor32": 2, "waves": 4096} for _ in meta]]
+    return meta, runs
+
+
+def test_residency_screen_uses_the_allocation_not_the_issued_bytes():
+    """A 2 MiB buffer read 512 times over (1 GiB issued) sits in the caches:
+    more than the HBM datasheet figure is expected there and never flagged.
+    The same rate over a 1 GiB buffer is flagged on every launch."""
+    s = sweeps.summarize_k_sweep(*_flat_sweep(2 << 20, 25000.0))
+    assert s["residency_flags"] == 0
+    s = sweeps.summarize_k_sweep(*_flat_sweep(1 << 30, 8500.0))
+    assert s["residency_flags"] == 8
+    s = sweeps.summarize_k_sweep(*_flat_sweep(1 << 30, 7900.0))
+    assert s["residency_flags"] == 0
+
+
+def test_summarize_k_sweep_needs_the_allocation():
+    import pytest
+    meta, runs = _flat_sweep(1 << 30, 7000.0)
+    del meta[3]["bytes"]
+    with pytest.raises(ValueError):
+        sweeps.summarize_k_sweep(meta, runs)
 
 
 def test_bench_refuses_more_than_one_gpu():
