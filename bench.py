@@ -309,6 +309,83 @@ def strict_cg_sweep(a, isw, sweeps, stats, buf, nbytes, L, waves_list, Ks):
     }
 
 
+def _reduce_lane_terms(kind, n, waves, waves_per_cu):
+    """Most terms one lane of the streaming sum adds in its TwoSum chain:
+    its share of the full wave-groups (8 loads per lane at 4 waves per CU,
+    4 above; FP8 adds one term per four vectors), one remainder vector and
+    the trailing elements."""
+    per_vec = {"f32": 4, "bf16": 8, "fp8_e4m3": 16}[kind]
+    eb = {"f32": 4, "bf16": 2, "fp8_e4m3": 1}[kind]
+    loads = 8 if waves_per_cu == 4 else 4
+    groups = (n * eb // 16) // (64 * loads)
+    g_lane = -(-groups // waves) if waves else 0
+    per_group = loads * per_vec if kind != "fp8_e4m3" else loads // 4
+    return g_lane * per_group + per_vec + 16
+
+
+def cpu_precision_hook(store, threads):
+    """The oracle's side of the precision rows: the exact sum (and sum |x|)
+    of each payload the GPU summed, from a host copy, computed in slices on
+    ``threads`` threads and combined exactly; the GPU sum's error against it
+    and the rigorous bound.  Timings go to ``store`` (part of the CPU
+    baseline)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import fpsum
+
+    def exact(kind, host, absolute):
+        if kind == "f32":
+            b = host.view(np.uint32)
+            b = b & np.uint32(0x7FFFFFFF) if absolute else b
+            fn = lambda a: fpsum.exact_sum_f32_bits(a, rational=True)
+        elif kind == "bf16":
+            b = host.view(np.uint16)
+            b = b & np.uint16(0x7FFF) if absolute else b
+            fn = lambda a: fpsum.exact_sum_bf16_bits(a, rational=True)
+        else:
+            b = host & np.uint8(0x7F) if absolute else host
+            fn = lambda a: fpsum.exact_sum_e4m3_hist(a, rational=True)
+        step = 1 << 24
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(fn, [b[i:i + step] for i in range(0, b.size, step)]))
+        return sum(parts)
+
+    def hook(kind, payload, n_el, row):
+        host = payload.cpu().numpy()
+        t0 = time.perf_counter()
+        s_exact = exact(kind, host, False)
+        t1 = time.perf_counter()
+        abs_sum = float(exact(kind, host, True))
+        del host
+        from fractions import Fraction
+        err = abs(Fraction(row["sum"]) - s_exact)
+        n_lane = _reduce_lane_terms(kind, n_el, row["waves"], row["waves_per_cu"])
+        bound = fpsum.sum2_bound(abs_sum, n_lane, 8, row["grid_wgs"])
+        store[kind] = {"exact_sum": float(s_exact), "seconds": t1 - t0,
+                       "gbps": payload.numel() / (t1 - t0) / 1e9, "threads": threads}
+        return {"exact_sum": float(s_exact), "abs_err": float(err),
+                "rel_err": float(err) / abs_sum if abs_sum else 0.0,
+                "bound": bound, "within_bound": float(err) <= bound}
+    return hook
+
+
+def cpu_batch_verifier(store, threads):
+    """The oracle's side of the batched row: every launch's sinks against
+    the global sums of the words it read (its issued prefix of its point),
+    computed on ``threads`` threads; the time goes to ``store``."""
+    from oracle import checksums
+
+    def verify(checks):
+        t0 = time.perf_counter()
+        want = checksums.range_sinks_many([c[:3] for c in checks], threads=threads)
+        store["seconds"] = time.perf_counter() - t0
+        store["threads"] = threads
+        store["words"] = sum(n for _, _, n in {c[:3] for c in checks})
+        store["gbps"] = 4 * store["words"] / store["seconds"] / 1e9
+        return [w == (c[3], c[4]) for w, c in zip(want, checks)]
+    return verify
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--cpu-oracle-worker":
         return cpu_oracle_worker(sys.argv[2])
@@ -514,6 +591,13 @@ def main():
     del buf
     if not a.no_extras:
         result["rows"] = run_extras(a, isw, sweeps, best_w=best_w)
+        # the oracle's exact sums behind the precision rows' errors
+        prec = result["rows"].pop("c5b_cpu_oracle", None)
+        if prec and "cpu_baseline" in result:
+            result["cpu_baseline"]["precision"] = prec
+        bat = result["rows"].pop("c5a_cpu_oracle", None)
+        if bat and "cpu_baseline" in result:
+            result["cpu_baseline"]["batched"] = bat
     detail = a.json_out or os.path.join("gpurun_out", "bench_detail.json")
     report.emit(result, detail, sys.stdout)
     return 0
@@ -573,14 +657,22 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         del buf
     if only in (None, "c5a"):
         t = time.perf_counter()
-        rows["c5a_batched"] = sweeps.batched_autotuned()
+        verify = None
+        if not a.no_cpu_baseline:
+            vstore = rows.setdefault("c5a_cpu_oracle", {})
+            verify = cpu_batch_verifier(vstore, max(1, min(16, os.cpu_count() or 1)))
+        rows["c5a_batched"] = sweeps.batched_autotuned(verify=verify)
         rows["c5a_batched"]["wall_s"] = time.perf_counter() - t
     if only in (None, "c5b"):
         t = time.perf_counter()
         fixed = None
         if a.c5b_waves:
             fixed = {k: int(v) for k, v in (kv.split("=") for kv in a.c5b_waves.split(","))}
-        rows["c5b_precision"] = sweeps.precision_sum(waves_fixed=fixed)
+        hook = None
+        if not a.no_cpu_baseline:
+            store = rows.setdefault("c5b_cpu_oracle", {})
+            hook = cpu_precision_hook(store, max(1, min(16, os.cpu_count() or 1)))
+        rows["c5b_precision"] = sweeps.precision_sum(waves_fixed=fixed, inspect=hook)
         rows["c5b_precision"]["wall_s"] = time.perf_counter() - t
     if only in (None, "next"):
         t = time.perf_counter()

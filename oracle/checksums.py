@@ -164,3 +164,50 @@ def two_stream_regions(n_vec_total):
     """
     half = n_vec_total // 2
     return (0, half), (half, n_vec_total - half)
+
+
+def range_sinks(seed, word_start, n_words, chunk=1 << 22):
+    """Global (sum32, xor32) of the seeded buffer's words
+    [word_start, word_start + n_words).
+
+    A launch that reads a contiguous region exactly once (a pass with no
+    wrap: Q wave-groups of K*64 consecutive vectors from the region's
+    start) folds exactly these words, and both sinks are associative and
+    commutative, so this is its global result whatever the dealing of
+    groups to waves."""
+    s = 0
+    x = 0
+    for a in range(word_start, word_start + n_words, chunk):
+        w = splitmix.words(seed, a, min(chunk, word_start + n_words - a))
+        s += int(w.astype(np.uint64).sum())
+        x ^= int(np.bitwise_xor.reduce(w)) if w.size else 0
+    return s & 0xFFFFFFFF, x
+
+
+def range_sinks_many(ranges, threads=1, piece=1 << 24):
+    """``range_sinks`` of many (seed, word_start, n_words) ranges, in
+    pieces of at most ``piece`` words evaluated on ``threads`` threads
+    (NumPy releases the interpreter lock inside its array loops); the
+    pieces of a range are combined with the sinks' own operators.  Equal
+    ranges are computed once."""
+    from concurrent.futures import ThreadPoolExecutor
+    uniq = sorted(set(ranges))
+    tasks = []
+    for k, (seed, start, n) in enumerate(uniq):
+        for a in range(start, start + n, piece):
+            tasks.append((k, seed, a, min(piece, start + n - a)))
+
+    def run(t):
+        return t[0], range_sinks(t[1], t[2], t[3])
+
+    if threads > 1:
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(run, tasks))
+    else:
+        parts = [run(t) for t in tasks]
+    acc = [[0, 0] for _ in uniq]
+    for k, (s, x) in parts:
+        acc[k][0] = (acc[k][0] + s) & 0xFFFFFFFF
+        acc[k][1] ^= x
+    got = {r: tuple(a) for r, a in zip(uniq, acc)}
+    return [got[r] for r in ranges]

@@ -24,7 +24,7 @@ REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step
 # Optional sections, dropped last-first if the line would exceed the limit.
 OPTIONAL = ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
             "peak_K_at_best", "decline_2_8_at_best", "paper_like", "strict_cg",
-            "gap", "eager", "c5a", "c5b", "streaming_gate", "detail")
+            "gap", "eager", "c5a", "c5b", "streaming_gate", "f4", "detail")
 
 
 def _r(x, nd=4):
@@ -125,9 +125,9 @@ def compact(result, detail_path=None):
                                       "paper_like_paired_decline_median"), 4)
     gap = r.get("gap")
     if isinstance(gap, dict):
-        out["gap"] = _pick(gap, ("hbm_latency_ns", "ceiling_frac_of_peak",
-                                 "frac_of_ceiling", "tail_loss", "residual_frac",
-                                 "kernel_frac"), 4)
+        out["gap"] = _pick(gap, ("hbm_latency_ns", "kernel_frac", "ceiling_frac_of_peak",
+                                 "body_frac_of_ceiling", "tail_loss",
+                                 "frac_of_ceiling"), 4)
     ea = r.get("eager_sweep")
     if isinstance(ea, dict):
         out["eager"] = _pick(ea, ("step_ms", "aggregate_gbps", "dispatch_event_gbps"), 1)
@@ -138,6 +138,12 @@ def compact(result, detail_path=None):
     c5b = _c5b(rows.get("c5b_precision"))
     if c5b:
         out["c5b"] = c5b
+    f4 = rows.get("f4_regime_map")
+    if isinstance(f4, dict) and isinstance(f4.get("backends"), dict):
+        # [saturating, rising-censored, peak-decline] curves per backend
+        out["f4"] = {name: [b["counts"].get(k, 0) for k in
+                            ("saturating", "rising-censored", "peak-decline")]
+                     for name, b in f4["backends"].items()}
     sg = r.get("streaming_gate")
     if isinstance(sg, dict):
         out["streaming_gate"] = _pick(sg, ("median_gbps", "median_frac",

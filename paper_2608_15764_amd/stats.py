@@ -154,7 +154,7 @@ def front_duplicates(blocked, K, n_waves, Q, n_vec, max_iters=64):
     return dup / total if total else 0.0
 
 
-def tail_loss(t0, t1):
+def idle_slots(t0, t1):
     """Share of the wave slots left idle inside a launch's window:
     1 - sum of wave durations / (waves x window), from the per-wave start
     and end clock readings.  Zero when every wave runs the whole window."""
@@ -169,6 +169,38 @@ def tail_loss(t0, t1):
     return 1.0 - busy / (n * win)
 
 
+def tail_loss(t0, t1, wave_bytes, q=0.1):
+    """Bandwidth lost to the end of a launch, from its per-wave records.
+
+    Each wave is taken to move its ``wave_bytes`` at an even rate between
+    its start and end readings.  The body rate is the launch's rate over
+    the interval in which every wave has started and fewer than a fraction
+    ``q`` of them has finished; the window rate is all bytes over the whole
+    window.  The tail loss is 1 - window rate / body rate: zero when the
+    launch keeps its body rate to the end, and the share of the window's
+    potential lost when waves finish unevenly and the rest cannot make up
+    for them.  None if the body interval is empty."""
+    n = len(t0)
+    if n == 0:
+        return None
+    a = max(t0)
+    ends = sorted(t1)
+    b = ends[min(n - 1, int(q * n))]
+    win = max(t1) - min(t0)
+    if b <= a or win <= 0:
+        return None
+    moved = 0.0
+    for s, e, nb in zip(t0, t1, wave_bytes):
+        if e > s:
+            ov = min(e, b) - max(s, a)
+            if ov > 0:
+                moved += nb * ov / (e - s)
+    body = moved / (b - a)
+    if body <= 0:
+        return None
+    return 1.0 - (sum(wave_bytes) / win) / body
+
+
 def littles_ceiling_gbps(in_flight, latency_ns, peak_gbps=HBM_PEAK_GBPS):
     """Little's-law ceiling of a cell: the smaller of the datasheet figure
     and bytes in flight over the round-trip latency (bytes/ns = GB/s)."""
@@ -181,27 +213,56 @@ def gap_split(cells, peak_gbps=HBM_PEAK_GBPS):
     """Where a sweep's distance from the datasheet figure goes.
 
     ``cells``: dicts with the cell's issued ``bytes``, its measured ``gbps``,
-    its Little's-law ``ceiling_gbps`` and its ``tail_loss``.  Times are
-    summed over the cells (each cell's bytes at its own rate), so
+    its Little's-law ``ceiling_gbps`` and its ``tail_loss`` (see
+    :func:`tail_loss`; the cell's body rate is gbps / (1 - tail_loss)).
+    Times are summed over the cells (each cell's bytes at its own rate), so
+    the three factors multiply exactly:
 
-        kernel_frac = ceiling_frac_of_peak * (1 - tail_loss) * residual_frac
+        kernel_frac = ceiling_frac_of_peak * body_frac_of_ceiling
+                      * (1 - tail_loss)
 
-    where ceiling_frac_of_peak is the time at the datasheet rate over the
-    time at every cell's ceiling (what offering too few bytes in flight
-    costs by design), tail_loss is the time-weighted idle share of the wave
-    slots, and residual_frac is what is left unexplained."""
+    ceiling_frac_of_peak  time at the datasheet rate / time at every cell's
+                          ceiling: what offering too few bytes in flight
+                          costs by design;
+    body_frac_of_ceiling  time at the ceilings / time at the body rates:
+                          how far the memory system stays below the ceiling
+                          while every wave is running (the residual);
+    tail_loss             1 - time at the body rates / measured time: what
+                          the uneven finish of the static equal split costs.
+    """
     if not cells:
         raise ValueError("no cells")
     t_meas = sum(c["bytes"] / c["gbps"] for c in cells)
+    t_body = sum(c["bytes"] * (1.0 - c["tail_loss"]) / c["gbps"] for c in cells)
     t_ceil = sum(c["bytes"] / c["ceiling_gbps"] for c in cells)
     t_peak = sum(c["bytes"] / peak_gbps for c in cells)
-    tail = sum(c["bytes"] / c["gbps"] * c["tail_loss"] for c in cells) / t_meas
-    kernel = t_peak / t_meas
-    ceil_frac = t_peak / t_ceil
-    of_ceiling = t_ceil / t_meas
-    return {"kernel_frac": kernel, "ceiling_frac_of_peak": ceil_frac,
-            "frac_of_ceiling": of_ceiling, "tail_loss": tail,
-            "residual_frac": of_ceiling / (1.0 - tail) if tail < 1 else None}
+    return {"kernel_frac": t_peak / t_meas,
+            "ceiling_frac_of_peak": t_peak / t_ceil,
+            "body_frac_of_ceiling": t_ceil / t_body,
+            "tail_loss": 1.0 - t_body / t_meas,
+            "frac_of_ceiling": t_ceil / t_meas}
+
+
+def line_coverage(alloc_bytes, vec_bytes, issued_loads, line=128):
+    """Exact 128-byte-line coverage of a cell (Section 4.2, "Allocation-size
+    sweep": with no address trace the paper can only bound its unique
+    coverage by issued volume over allocation).
+
+    A cell's loads read the vector stream 0, 1, ..., issued - 1 modulo the
+    allocation's vector count (every group is K consecutive 64-lane
+    segments, and the groups below Q are consecutive), so after m whole
+    passes and a remainder of r vectors, the lines of the first r vectors
+    are read m + 1 times and all others m times.  Issued loads and the
+    vector count are multiples of 64, so r covers whole lines."""
+    n_vec = alloc_bytes // vec_bytes
+    alloc_lines = alloc_bytes // line
+    m, r = divmod(issued_loads, n_vec)
+    r_lines = r * vec_bytes // line
+    unique = alloc_lines if m else r_lines
+    total = m * alloc_lines + r_lines
+    return {"unique_lines": unique, "alloc_lines": alloc_lines, "line_reads": total,
+            "re_reads": total - unique, "max_reads": m + (1 if r else 0),
+            "coverage": unique / alloc_lines}
 
 
 def summarize_curve(samples):

@@ -236,9 +236,12 @@ def allocation_sweep(sizes, Ks=(1, 2, 4, 8), waves_list=(16,), L=1 << 30,
         s_meta = [meta[i] for i in idx]
         s_runs = [[run[i] for i in idx] for run in runs]
         summ = summarize_k_sweep(s_meta, s_runs)
+        issued = {m["K"]: r["issued_loads"] for m, r in zip(s_meta, s_runs[0])}
         out[size] = {
             "issued_bytes": s_runs[0][0]["issued_bytes"],
             "volume_to_allocation": s_runs[0][0]["issued_bytes"] / size,
+            # exact unique-line coverage of every K's cell, from the address map
+            "coverage": {K: _coverage_row(size, 16, n) for K, n in sorted(issued.items())},
             "curves": {w: {"median_gbps": c["median_gbps"],
                            "decline_2_8": c.get("decline_2_8"),
                            "by_order": c["by_order"]}
@@ -248,6 +251,14 @@ def allocation_sweep(sizes, Ks=(1, 2, 4, 8), waves_list=(16,), L=1 << 30,
         }
     del buf
     return out
+
+
+def _coverage_row(alloc_bytes, vec_bytes, issued_loads):
+    c = stats.line_coverage(alloc_bytes, vec_bytes, issued_loads)
+    return {"coverage": round(c["coverage"], 6), "re_reads": c["re_reads"],
+            "max_reads": c["max_reads"],
+            "re_read_frac": round(c["re_reads"] / c["line_reads"], 6)
+            if c["line_reads"] else 0.0}
 
 
 # ------------------------------------------------- path comparison (C4)
@@ -348,11 +359,13 @@ def size_class(nbytes):
     return len(SIZE_CLASS_EDGES)
 
 
-# Every point must be one whole pass (64 K V divides its size, a multiple of
-# 64 KiB), which holds for the powers of two only: K = 7, next to the
-# sweep's best cells, would leave up to 7 KiB of a point unread.
-DEFAULT_SPACE = {"vec_widths": [16, 8], "Ks": [1, 2, 4, 8, 16],
-                 "waves_per_cu": [4, 8, 16, 32],
+# The tuner's candidates: every vector width, K = 1..16, 1..8 waves per SIMD
+# and every cache policy.  A point whose size 64 K V does not divide is read
+# up to its last whole wave-group (the fixed-work rule), at most 64 K V - V
+# bytes short of the whole point; the issued bytes are what is timed and
+# what the sinks cover.
+DEFAULT_SPACE = {"vec_widths": [4, 8, 16], "Ks": list(range(1, 17)),
+                 "waves_per_cu": [4 * w for w in range(1, 9)],
                  "policies": [isw.CACHE_DEFAULT, isw.CACHE_NT,
                               isw.CACHE_BYPASS_L1, isw.CACHE_BYPASS_L1_NT]}
 
@@ -396,8 +409,17 @@ def autotune(buf_for_size, sizes, space=None, reps=3, cache_path=None,
 
 
 def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1),
-                      seed=SEED_BASE + 4, cache_path=None, space=None):
-    sizes = point_sizes(n_points)
+                      seed=SEED_BASE + 4, cache_path=None, space=None, verify=None,
+                      hi_log2=31):
+    """64 sweep points of uneven size (1 MiB .. 2 GiB), laid out back to
+    back in one seeded buffer, each read once per pass at its size class's
+    tuned (V, K, waves, policy): captured once as a hipGraph and replayed
+    ``n`` times, against the same points launched one by one at the untuned
+    default.  ``verify``, if given, is called with one (seed, first word,
+    words, sum32, xor32) tuple per launch of the first tuned replay and of
+    the first untuned pass, and returns one bool per tuple: whether those
+    sinks are the ones the words' oracle gives."""
+    sizes = point_sizes(n_points, hi_log2=hi_log2)
     offs, off = [], 0
     for s in sizes:
         offs.append(off)
@@ -431,41 +453,68 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
             p_runs.append(isw.sweep_run(plain))
     finally:
         isw.sweep_graph_destroy(graph)
-    sums_ok = all((a["sum32"], a["xor32"]) == (b["sum32"], b["xor32"])
-                  for a, b in zip(g_runs[0], p_runs[0]))
     pts = []
     for i, s in enumerate(sizes):
         gb = _median([r[i]["gbps"] for r in g_runs])
         pb = _median([r[i]["gbps"] for r in p_runs])
-        pts.append({"bytes": s, "batched_gbps": gb, "plain_gbps": pb,
+        t = table[size_class(s)]
+        pts.append({"bytes": s, "issued_bytes": g_runs[0][i]["issued_bytes"],
+                    "K": t["K"], "vec_width": t["vec_width"],
+                    "waves_per_cu": t["waves_per_cu"], "cache_policy": t["cache_policy"],
+                    "batched_gbps": gb, "plain_gbps": pb,
                     "hbm_targeted": s > stats.INFINITY_CACHE_BYTES})
-    hbm = [p for p in pts if p["hbm_targeted"]]
+    issued = sum(p["issued_bytes"] for p in pts)
+    hbm = [i for i, p in enumerate(pts) if p["hbm_targeted"]]
+    # every HBM-targeted point's bytes over its own median window
+    hbm_bytes = sum(pts[i]["issued_bytes"] for i in hbm)
+    hbm_ns = sum(_median([r[i]["window_ns"] for r in g_runs]) for i in hbm)
     plain_ms = _median([sum(r["event_ms"] for r in run) for run in p_runs])
     out = {
         "sizes": len(sizes),
         "total_bytes": off,
+        "issued_bytes": issued,
         "tuned": {str(k): v for k, v in table.items()},
+        "space": {k: (v if k != "policies" else [int(p) for p in v])
+                  for k, v in (space or DEFAULT_SPACE).items()},
         "points": pts,
         "graph_ms": _median(g_ms),
         "plain_kernel_ms_sum": plain_ms,
-        "batched_peak_gbps": max(p["batched_gbps"] for p in hbm),
-        "plain_peak_gbps": max(p["plain_gbps"] for p in hbm),
-        "batched_aggregate_gbps": off / (_median(g_ms) * 1e6),
-        "checksums_equal": sums_ok,
+        # the headline: the whole batch's issued bytes over the graph's time
+        "batched_aggregate_gbps": issued / (_median(g_ms) * 1e6),
+        "hbm_points": len(hbm),
+        "hbm_aggregate_gbps": hbm_bytes / hbm_ns if hbm_ns else None,
+        "batched_best_point_gbps": max(p["batched_gbps"] for i, p in enumerate(pts)
+                                       if i in hbm) if hbm else None,
+        "plain_aggregate_gbps": sum(r["issued_bytes"] for r in p_runs[0]) / (plain_ms * 1e6),
+        "plain_best_point_gbps": max(p["plain_gbps"] for i, p in enumerate(pts)
+                                     if i in hbm) if hbm else None,
     }
-    out["batched_peak_frac"] = out["batched_peak_gbps"] / stats.HBM_PEAK_GBPS
-    out["plain_peak_frac"] = out["plain_peak_gbps"] / stats.HBM_PEAK_GBPS
+    out["batched_aggregate_frac"] = out["batched_aggregate_gbps"] / stats.HBM_PEAK_GBPS
+    if out["hbm_aggregate_gbps"]:
+        out["hbm_aggregate_frac"] = out["hbm_aggregate_gbps"] / stats.HBM_PEAK_GBPS
+    if verify is not None:
+        checks = []
+        for runs in (g_runs[0], p_runs[0]):
+            for o, r in zip(offs, runs):
+                checks.append((seed, o // 4, r["issued_bytes"] // 4, r["sum32"], r["xor32"]))
+        ok = verify(checks)
+        out["matches_oracle"] = bool(all(ok))
+        out["points_checked"] = len(ok)
+        out["mismatched_points"] = [i for i, v in enumerate(ok) if not v]
     del big
     return out
 
 
 # ----------------------------------------------- precision reduction (C5b)
 def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 32),
-                  seed=SEED_BASE + 5, waves_fixed=None):
+                  seed=SEED_BASE + 5, waves_fixed=None, inspect=None):
     """Streaming FP32 / BF16 / FP8 sums of N(0,1) payloads.  The occupancy
     is tuned per payload type (median of 3 launches per choice), then n
     launches are timed at the chosen occupancy.  ``waves_fixed`` ({kind:
-    waves_per_cu}) skips the tuning for the kinds it names."""
+    waves_per_cu}) skips the tuning for the kinds it names.  ``inspect``,
+    if given, is called as inspect(kind, payload, n_elements, row) after a
+    kind's launches, while its payload is still on the device; what it
+    returns (a dict) is merged into the kind's row."""
     import synth
     out = {}
     for kind, dt in (("f32", isw.F32), ("bf16", isw.BF16), ("fp8_e4m3", isw.FP8_E4M3)):
@@ -493,7 +542,10 @@ def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 
                      "waves_per_cu": best_w,
                      "tuning_gbps": {w: round(g, 1) for w, g in tune.items()},
                      "median_gbps": _median(gs),
-                     "frac_of_hbm_peak": _median(gs) / stats.HBM_PEAK_GBPS}
+                     "frac_of_hbm_peak": _median(gs) / stats.HBM_PEAK_GBPS,
+                     "waves": r["waves"], "grid_wgs": r["grid_wgs"]}
+        if inspect is not None:
+            out[kind].update(inspect(kind, p, n_el, out[kind]))
         del p
     return out
 
@@ -554,7 +606,10 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
             summ = summarize_k_sweep(meta, runs)
             c = summ["curves"][waves_per_cu]
             n_waves = runs[0][0]["waves"]
+            issued = {m["K"]: r["issued_loads"] for m, r in zip(meta, runs[0])}
             row[oname] = {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
+                          "coverage": {K: _coverage_row(size, 16, n)
+                                       for K, n in sorted(issued.items())},
                           "front_duplicates": {
                               K: round(stats.front_duplicates(
                                   order == isw.ORDER_BLOCKED, K, n_waves, L // (64 * K),
@@ -569,47 +624,72 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
 
 
 # ----------------------------------------------- regime map (next row f4)
+REGIME_BACKENDS = (("hbm", GIB), ("infinity_cache", 128 * MIB), ("l2", 4 * MIB))
+
+
 def regime_map(waves_list=(4, 8, 12, 16, 20, 24, 28, 32), widths=(4, 8, 16),
-               Ks=range(1, 17), half_grid=True, nbytes=GIB,
-               policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 7):
+               Ks=range(1, 17), half_grid=True, backends=REGIME_BACKENDS,
+               work_bytes=GIB, policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 7):
     """Response curves over occupancy x vector width (x full / half-CU
     grids), each classified saturating / rising-censored / peak-decline by
-    the 95 % plateau rule with a three-cell tail."""
-    buf = device_buffer(nbytes, seed)
+    the 95 % plateau rule with a three-cell tail, on every backend: a buffer
+    far above the caches (HBM), one inside the 256 MiB last-level cache and
+    one inside the 4 MiB L2 of an XCD (Section 4.2, "Prevalence", compares
+    the prevalence of the decline on the L2-targeted and the HBM backends).
+
+    Every curve reads the same logical volume, ``work_bytes`` (half of it on
+    the half grid), wrapping over the smaller buffers.  A pass runs every K
+    ascending, then descending; after one warm-up pass ``n`` passes are
+    timed, so every cell has 2n launches, whose median is its figure."""
     info = isw.sweep_device_info()
     grids = [0] + ([info["num_cus"] // 2] if half_grid else [])
-    curves = {}
-    counts = {"saturating": 0, "rising-censored": 0, "peak-decline": 0, "infeasible": 0}
-    for g in grids:
-        for V in widths:
-            for w in waves_list:
-                L = nbytes // V if g == 0 else nbytes // (2 * V)
-                cells = []
-                keep = []
-                for K in Ks:
-                    c = isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
-                                      grid_wgs=(g * w // 4) if g else 0)
-                    if _feasible(c):
-                        cells.append(c)
-                        keep.append(K)
-                if len(keep) < 3:
-                    counts["infeasible"] += 1
-                    continue
-                arr = isw.cell_array(cells)
-                samples = {K: [] for K in keep}
-                for _ in range(n):
-                    for K, r in zip(keep, isw.sweep_run(arr)):
-                        samples[K].append(r["gbps"])
-                med = stats.per_k_medians(samples)
-                reg = stats.classify(med)
-                counts[reg] += 1
-                key = f"{'half' if g else 'full'}_V{V}_w{w}"
-                curves[key] = {"regime": reg, "peak_K": stats.peak_k(med),
-                               "peak_gbps": round(max(med.values()), 1),
-                               "decline_2_8": (stats.decline(med[2], med[8])
-                                               if 2 in med and 8 in med else None)}
-    del buf
-    return {"counts": counts, "curves": curves}
+    out = {}
+    for name, nbytes in backends:
+        buf = device_buffer(nbytes, seed)
+        curves = {}
+        counts = {"saturating": 0, "rising-censored": 0, "peak-decline": 0,
+                  "infeasible": 0}
+        for g in grids:
+            for V in widths:
+                for w in waves_list:
+                    L = work_bytes // V if g == 0 else work_bytes // (2 * V)
+                    keep = []
+                    for K in Ks:
+                        c = isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
+                                          grid_wgs=(g * w // 4) if g else 0)
+                        if _feasible(c):
+                            keep.append(K)
+                    if len(keep) < 3:
+                        counts["infeasible"] += 1
+                        continue
+                    seq = keep + keep[::-1]
+                    cells = [isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
+                                           grid_wgs=(g * w // 4) if g else 0) for K in seq]
+                    arr = isw.cell_array(cells)
+                    isw.sweep_run(arr, raw=True)                 # warm-up pass
+                    samples = {K: [] for K in keep}
+                    by_order = {"asc": {K: [] for K in keep}, "rev": {K: [] for K in keep}}
+                    for _ in range(n):
+                        for i, (K, r) in enumerate(zip(seq, isw.sweep_run(arr))):
+                            samples[K].append(r["gbps"])
+                            by_order["asc" if i < len(keep) else "rev"][K].append(r["gbps"])
+                    med = stats.per_k_medians(samples)
+                    reg = stats.classify(med)
+                    counts[reg] += 1
+                    key = f"{'half' if g else 'full'}_V{V}_w{w}"
+                    curves[key] = {
+                        "regime": reg, "peak_K": stats.peak_k(med),
+                        "peak_gbps": round(max(med.values()), 1),
+                        "decline_2_8": (stats.decline(med[2], med[8])
+                                        if 2 in med and 8 in med else None),
+                        "regime_by_order": {o: stats.classify(stats.per_k_medians(v))
+                                            for o, v in by_order.items()}}
+        out[name] = {"bytes": nbytes, "counts": counts, "curves": curves,
+                     "launches_per_cell": 2 * n}
+        del buf
+    return {"backends": out,
+            "counts": {name: v["counts"] for name, v in out.items()},
+            "work_bytes": work_bytes}
 
 
 # ------------------------------------------- latency ladder (next row f1)
@@ -778,17 +858,26 @@ def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
             if g is None:
                 continue
             opts = isw.make_opts(cache_policy=policy, wave_out=rec)
+            isw.sweep_plain(buf, nbytes, K, vec_width, w, L, opts)     # warm-up
             r = isw.sweep_plain(buf, nbytes, K, vec_width, w, L, opts)
             a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
-            tl = stats.tail_loss(a["t0"].astype("int64").tolist(),
-                                 a["t1"].astype("int64").tolist())
+            t0 = a["t0"].astype("int64").tolist()
+            t1 = a["t1"].astype("int64").tolist()
+            # wave v handles groups v, v + n, ... below Q (round robin)
+            n, Q = r["waves"], r["issued_loads"] // (64 * K)
+            gb = 64 * K * vec_width
+            wb = [((Q - v + n - 1) // n) * gb for v in range(n)]
+            tl = stats.tail_loss(t0, t1, wb)
+            if tl is None:
+                tl = 0.0
             fl = stats.in_flight_bytes(r["waves"], K, vec_width)
             ceil = stats.littles_ceiling_gbps(fl, latency_ns)
             c = {"bytes": r["issued_bytes"], "gbps": g, "ceiling_gbps": ceil,
                  "tail_loss": tl}
             cells.append(c)
             rows[K] = {"gbps": round(g, 1), "ceiling_gbps": round(ceil, 1),
-                       "frac_of_ceiling": round(g / ceil, 4), "tail_loss": round(tl, 4)}
+                       "body_gbps": round(g / (1.0 - tl), 1), "tail_loss": round(tl, 4),
+                       "idle_slots": round(stats.idle_slots(t0, t1), 4)}
         if rows:
             split = stats.gap_split([c for c in cells[-len(rows):]])
             per_w[w] = {"cells": rows,
@@ -799,8 +888,10 @@ def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
     out["hbm_latency_ns"] = round(latency_ns, 1)
     out["by_waves_per_cu"] = per_w
     out["method"] = ("ceiling = min(8 TB/s, bytes in flight / unloaded HBM latency); "
-                     "tail loss = 1 - sum of wave durations / (waves x window), one "
-                     "untimed launch per cell; times summed over cells")
+                     "body rate = rate while every wave runs (all started, < 10 % "
+                     "finished), from one untimed launch per cell with per-wave clock "
+                     "records; tail loss = 1 - window rate / body rate; times summed "
+                     "over cells")
     return out
 
 

@@ -286,6 +286,38 @@ def test_batched_points_full_size():
     torch.cuda.empty_cache()
 
 
+def test_autotuned_batch_matches_oracle():
+    """The autotuned batch over the tuner's whole space (V in {4, 8, 16},
+    K = 1..16, 1..8 waves per SIMD, every cache policy): every point of the
+    tuned graph, and of the untuned pass beside it, carries the sinks of
+    exactly the words it read, its issued prefix 64 K floor(L / 64 K)
+    vectors of its point, whatever K the tuner chose."""
+    import os
+    threads = max(1, min(16, os.cpu_count() or 1))
+    seen = []
+
+    def verify(checks):
+        seen.extend(checks)
+        want = checksums.range_sinks_many([c[:3] for c in checks], threads=threads)
+        return [w == (c[3], c[4]) for w, c in zip(want, checks)]
+
+    out = sweeps.batched_autotuned(n=2, verify=verify)
+    print("tuned:", out["tuned"], flush=True)
+    assert out["matches_oracle"], out["mismatched_points"]
+    assert out["points_checked"] == 128 == len(seen)
+    space = sweeps.DEFAULT_SPACE
+    assert space["Ks"] == list(range(1, 17)) and space["vec_widths"] == [4, 8, 16]
+    assert space["waves_per_cu"] == [4, 8, 12, 16, 20, 24, 28, 32]
+    for p in out["points"]:
+        V, K = p["vec_width"], p["K"]
+        assert V in space["vec_widths"] and K in space["Ks"]
+        assert p["waves_per_cu"] in space["waves_per_cu"]
+        L = p["bytes"] // V
+        assert p["issued_bytes"] == 64 * K * (L // (64 * K)) * V
+    assert out["batched_aggregate_gbps"] > 0 and out["hbm_aggregate_gbps"] > 0
+    torch.cuda.empty_cache()
+
+
 def test_autotuner_picks_a_candidate():
     nbytes = 256 << 20
     buf = sweeps.device_buffer(nbytes, 9)
@@ -310,19 +342,18 @@ def test_precision_sum_full_size(kind):
     host = p.cpu().numpy()
     del p
     torch.cuda.empty_cache()
+    # exact sums of the stored values and of their magnitudes (sign bit off)
     if kind == "fp8_e4m3":
-        exact = fpsum.exact_sum_e4m3(host)
-        # sum |x| exactly from the integer multiples of 2**-9
-        t = np.abs(np.array([fpsum.e4m3_scaled_int(c)[0] for c in range(256)],
-                            dtype=np.int64))
-        absx = float(sum(int(t[host[s:s + (1 << 24)]].sum())
-                         for s in range(0, host.size, 1 << 24))) * 2.0**-9
+        exact = fpsum.exact_sum_e4m3_hist(host)
+        absx = fpsum.exact_sum_e4m3_hist(host & np.uint8(0x7F))
+    elif kind == "bf16":
+        bits = host.view(np.uint16)
+        exact = fpsum.exact_sum_bf16_bits(bits)
+        absx = fpsum.exact_sum_bf16_bits(bits & np.uint16(0x7FFF))
     else:
-        bits = host.view(np.uint32) if kind == "f32" else host.view(np.uint16)
-        vals = bits.view(np.float32) if kind == "f32" else \
-            (bits.astype(np.uint32) << np.uint32(16)).view(np.float32)
-        exact = fpsum.exact_sum(vals)
-        absx = float(np.abs(vals, dtype=np.float64).sum())
+        bits = host.view(np.uint32)
+        exact = fpsum.exact_sum_f32_bits(bits)
+        absx = fpsum.exact_sum_f32_bits(bits & np.uint32(0x7FFFFFFF))
     for got, res, w in ((s1, r, 32), (s4, r4, 4)):
         err = abs(got - exact)
         print(f"{kind} at {w} waves/CU: gpu {got!r} exact {exact!r} |err| {err:.3e} "

@@ -165,3 +165,37 @@ def test_orders_partition_the_same_groups():
     a = checksums.combine(*checksums.per_wave(w, V, K, Q, nw))
     b = checksums.combine(*checksums.per_wave(w, V, K, Q, nw, order=plan.BLOCKED))
     assert a == b
+
+
+@pytest.mark.parametrize("V,K", [(16, 1), (16, 7), (8, 3), (4, 13), (16, 16)])
+def test_range_sinks_equal_a_one_pass_cell(V, K):
+    """A one-pass cell over a region (no wrap) reads exactly its issued
+    prefix once: the per-wave oracle's global sinks equal the range sums of
+    that prefix, for K that do not divide the region too."""
+    seed, base_words = 77, 1000
+    n_vec = (48 << 10) // V
+    words = splitmix.words(seed, 0, base_words + n_vec * V // 4)
+    region = words[base_words:]
+    Q = n_vec // (64 * K)
+    s, x = checksums.per_wave(region, V, K, Q, 24, n_vec=n_vec)
+    want = checksums.combine(s, x)
+    issued_words = Q * 64 * K * V // 4
+    assert checksums.range_sinks(seed, base_words, issued_words, chunk=999) == want
+
+
+def test_range_sinks_brute_force_and_empty():
+    seed = 3
+    got = checksums.range_sinks(seed, 17, 50, chunk=7)
+    s = sum(splitmix.word_int(seed, i) for i in range(17, 67)) & 0xFFFFFFFF
+    x = 0
+    for i in range(17, 67):
+        x ^= splitmix.word_int(seed, i)
+    assert got == (s, x)
+    assert checksums.range_sinks(seed, 5, 0) == (0, 0)
+
+
+def test_range_sinks_many_combines_pieces():
+    ranges = [(9, 0, 10000), (9, 123, 4567), (10, 5, 1), (9, 0, 10000), (9, 40, 0)]
+    want = [checksums.range_sinks(*r) for r in ranges]
+    assert checksums.range_sinks_many(ranges, threads=3, piece=1000) == want
+    assert checksums.range_sinks_many(ranges, threads=1, piece=333) == want

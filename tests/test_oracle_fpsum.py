@@ -134,3 +134,58 @@ def test_sum2_recovers_what_plain_fp32_loses():
     for v in x:
         plain = np.float32(plain + v)
     assert float(plain) != 1000.0
+
+
+# ------------------------------------------- the histogram exact sums
+def _finite_f32_bits(rng, n):
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    return b[((b >> 23) & 0xFF) != 0xFF]
+
+
+def test_f32_histogram_sum_matches_the_rational_sum():
+    rng = np.random.default_rng(11)
+    bits = _finite_f32_bits(rng, 100000)            # every exponent, subnormals too
+    want = fpsum.exact_sum_rational(fpsum.decode_f32(bits))
+    assert fpsum.exact_sum_f32_bits(bits, chunk=4097, rational=True) == want
+    assert fpsum.exact_sum_f32_bits(bits) == float(want)
+    x = _wide(rng, 5000).astype(np.float32)
+    assert fpsum.exact_sum_f32_bits(x.view(np.uint32)) == math.fsum(x.astype(np.float64).tolist())
+
+
+def test_bf16_histogram_sum_matches_the_rational_sum():
+    rng = np.random.default_rng(12)
+    b = rng.integers(0, 2**16, 100000, dtype=np.uint32).astype(np.uint16)
+    b = b[((b >> 7) & 0xFF) != 0xFF]
+    want = fpsum.exact_sum_rational(fpsum.decode_bf16(b))
+    assert fpsum.exact_sum_bf16_bits(b, chunk=1000, rational=True) == want
+
+
+def test_e4m3_histogram_sum_matches_the_integer_sum():
+    rng = np.random.default_rng(13)
+    c = rng.integers(0, 256, 300000, dtype=np.uint32).astype(np.uint8)
+    c = c[(c != 0x7F) & (c != 0xFF)]
+    assert fpsum.exact_sum_e4m3_hist(c, chunk=999) == fpsum.exact_sum_e4m3(c)
+    assert fpsum.exact_sum_e4m3_hist(c, rational=True) * 512 == \
+        sum(fpsum.e4m3_scaled_int(int(v))[0] for v in c)
+
+
+def test_histogram_sums_special_cases():
+    # constant payloads sum to n * x; +x / -x pairs cancel; signed zeros
+    x = np.full(3001, np.float32(0.1))
+    assert fpsum.exact_sum_f32_bits(x.view(np.uint32), rational=True) == \
+        3001 * Fraction(float(np.float32(0.1)))
+    y = np.random.default_rng(14).standard_normal(5000).astype(np.float32)
+    both = np.concatenate([y, -y])
+    assert fpsum.exact_sum_f32_bits(both.view(np.uint32)) == 0.0
+    assert fpsum.exact_sum_f32_bits(np.array([0x80000000, 0], dtype=np.uint32)) == 0.0
+    # the smallest subnormals: 2**-149 (binary32) and 2**-133 (BF16)
+    assert fpsum.exact_sum_f32_bits(np.array([1, 1], dtype=np.uint32)) == 2.0**-148
+    assert fpsum.exact_sum_bf16_bits(np.array([1, 0x8001, 1], dtype=np.uint16)) == 2.0**-133
+    assert fpsum.exact_sum_e4m3_hist(np.array([0x7E, 0xFE, 0x01], dtype=np.uint8)) == 2.0**-9
+    assert fpsum.exact_sum_f32_bits(np.array([], dtype=np.uint32)) == 0.0
+    with pytest.raises(ValueError):
+        fpsum.exact_sum_f32_bits(np.array([0x7F800000], dtype=np.uint32))   # +inf
+    with pytest.raises(ValueError):
+        fpsum.exact_sum_bf16_bits(np.array([0x7FC0], dtype=np.uint16))     # NaN
+    with pytest.raises(ValueError):
+        fpsum.exact_sum_e4m3_hist(np.array([0x7F], dtype=np.uint8))

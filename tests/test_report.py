@@ -61,7 +61,7 @@ def full_result():
                      "mean_launch_us": 161.7, "timing": "hipEvent pair per replay",
                      "algorithmic_bytes_per_launch": 1073739296},
         "gap": {"kernel_frac": 0.84, "ceiling_frac_of_peak": 0.98,
-                "frac_of_ceiling": 0.857, "tail_loss": 0.12, "residual_frac": 0.974,
+                "frac_of_ceiling": 0.857, "tail_loss": 0.12, "body_frac_of_ceiling": 0.974,
                 "hbm_latency_ns": 360.1, "by_waves_per_cu": {w: {} for w in curves}},
         "eager_sweep": {"step_ms": 42.0, "aggregate_gbps": 6442.0,
                         "dispatch_event_gbps": 6678.0},
@@ -85,7 +85,12 @@ def full_result():
             "c5b_precision": {k: {"median_gbps": 7200.0, "frac_of_hbm_peak": 0.9,
                                   "abs_err": 1e-10, "rel_err": 1e-16, "within_bound": True}
                               for k in ("f32", "bf16", "fp8_e4m3")},
-            "f4_regime_map": {"counts": {"saturating": 30}, "curves": regime},
+            "f4_regime_map": {"counts": {"saturating": 30}, "curves": regime,
+                              "backends": {b: {"counts": {"saturating": 20,
+                                                          "rising-censored": 4,
+                                                          "peak-decline": 24},
+                                               "curves": regime}
+                                           for b in ("hbm", "infinity_cache", "l2")}},
         },
     }
 
@@ -116,6 +121,7 @@ def test_headline_line_fits_and_keeps_everything():
     assert set(d["c5b"]) == {"f32", "bf16", "fp8_e4m3"}
     assert d["gap"]["tail_loss"] == 0.12
     assert d["streaming_gate"]["verdict"] == "latency-bound"
+    assert d["f4"] == {b: [20, 4, 24] for b in ("hbm", "infinity_cache", "l2")}
     assert d["detail"] == "gpurun_out/bench_detail.json"
 
 
