@@ -126,8 +126,7 @@ def compact(result, detail_path=None):
     gap = r.get("gap")
     if isinstance(gap, dict):
         out["gap"] = _pick(gap, ("hbm_latency_ns", "kernel_frac", "ceiling_frac_of_peak",
-                                 "body_frac_of_ceiling", "tail_loss",
-                                 "frac_of_ceiling"), 4)
+                                 "tail_loss", "residual_frac", "frac_of_ceiling"), 4)
     ea = r.get("eager_sweep")
     if isinstance(ea, dict):
         out["eager"] = _pick(ea, ("step_ms", "aggregate_gbps", "dispatch_event_gbps"), 1)

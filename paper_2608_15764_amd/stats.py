@@ -169,36 +169,31 @@ def idle_slots(t0, t1):
     return 1.0 - busy / (n * win)
 
 
-def tail_loss(t0, t1, wave_bytes, q=0.1):
-    """Bandwidth lost to the end of a launch, from its per-wave records.
+def active_ceiling_gbps(t0, t1, in_flight_per_wave, latency_ns, peak_gbps=HBM_PEAK_GBPS):
+    """Little's-law ceiling of a launch given when its waves actually ran:
+    the time average, over the launch's window, of min(peak, bytes in
+    flight of the waves running at that moment / latency).
 
-    Each wave is taken to move its ``wave_bytes`` at an even rate between
-    its start and end readings.  The body rate is the launch's rate over
-    the interval in which every wave has started and fewer than a fraction
-    ``q`` of them has finished; the window rate is all bytes over the whole
-    window.  The tail loss is 1 - window rate / body rate: zero when the
-    launch keeps its body rate to the end, and the share of the window's
-    potential lost when waves finish unevenly and the rest cannot make up
-    for them.  None if the body interval is empty."""
+    Every wave keeps at most ``in_flight_per_wave`` bytes outstanding while
+    it runs and none after it ends, so the launch's rate at any moment is at
+    most that minimum, and its window rate at most this average.  With
+    every wave running for the whole window it is the cell's design ceiling;
+    waves that finish early lower it only where the rest no longer cover
+    the bandwidth-delay product."""
     n = len(t0)
     if n == 0:
-        return None
-    a = max(t0)
-    ends = sorted(t1)
-    b = ends[min(n - 1, int(q * n))]
-    win = max(t1) - min(t0)
-    if b <= a or win <= 0:
-        return None
-    moved = 0.0
-    for s, e, nb in zip(t0, t1, wave_bytes):
-        if e > s:
-            ov = min(e, b) - max(s, a)
-            if ov > 0:
-                moved += nb * ov / (e - s)
-    body = moved / (b - a)
-    if body <= 0:
-        return None
-    return 1.0 - (sum(wave_bytes) / win) / body
+        return 0.0
+    ev = sorted([(a, 1) for a in t0] + [(b, -1) for b in t1])
+    lo, hi = ev[0][0], max(t1)
+    if hi <= lo:
+        return min(peak_gbps, n * in_flight_per_wave / latency_ns)
+    area, active, last = 0.0, 0, lo
+    for t, d in ev:
+        if t > last:
+            area += (t - last) * min(peak_gbps, active * in_flight_per_wave / latency_ns)
+            last = t
+        active += d
+    return area / (hi - lo)
 
 
 def littles_ceiling_gbps(in_flight, latency_ns, peak_gbps=HBM_PEAK_GBPS):
@@ -212,34 +207,34 @@ def littles_ceiling_gbps(in_flight, latency_ns, peak_gbps=HBM_PEAK_GBPS):
 def gap_split(cells, peak_gbps=HBM_PEAK_GBPS):
     """Where a sweep's distance from the datasheet figure goes.
 
-    ``cells``: dicts with the cell's issued ``bytes``, its measured ``gbps``,
-    its Little's-law ``ceiling_gbps`` and its ``tail_loss`` (see
-    :func:`tail_loss`; the cell's body rate is gbps / (1 - tail_loss)).
-    Times are summed over the cells (each cell's bytes at its own rate), so
-    the three factors multiply exactly:
+    ``cells``: dicts with the cell's issued ``bytes``, its measured
+    ``gbps``, its Little's-law design ``ceiling_gbps`` (every wave running)
+    and its ``active_ceiling_gbps`` (the same with the waves that actually
+    ran, see :func:`active_ceiling_gbps`).  Times are summed over the cells
+    (each cell's bytes at a rate), so the three factors multiply exactly:
 
-        kernel_frac = ceiling_frac_of_peak * body_frac_of_ceiling
-                      * (1 - tail_loss)
+        kernel_frac = ceiling_frac_of_peak * (1 - tail_loss) * residual_frac
 
-    ceiling_frac_of_peak  time at the datasheet rate / time at every cell's
-                          ceiling: what offering too few bytes in flight
+    ceiling_frac_of_peak  time at the datasheet rate / time at the design
+                          ceilings: what offering too few bytes in flight
                           costs by design;
-    body_frac_of_ceiling  time at the ceilings / time at the body rates:
-                          how far the memory system stays below the ceiling
-                          while every wave is running (the residual);
-    tail_loss             1 - time at the body rates / measured time: what
-                          the uneven finish of the static equal split costs.
+    tail_loss             1 - time at the design ceilings / time at the
+                          active ceilings: what the uneven finish of the
+                          static equal split costs in ceiling;
+    residual_frac         time at the active ceilings / measured time: how
+                          far the memory system stays below what the
+                          running waves offer.
     """
     if not cells:
         raise ValueError("no cells")
     t_meas = sum(c["bytes"] / c["gbps"] for c in cells)
-    t_body = sum(c["bytes"] * (1.0 - c["tail_loss"]) / c["gbps"] for c in cells)
+    t_act = sum(c["bytes"] / c["active_ceiling_gbps"] for c in cells)
     t_ceil = sum(c["bytes"] / c["ceiling_gbps"] for c in cells)
     t_peak = sum(c["bytes"] / peak_gbps for c in cells)
     return {"kernel_frac": t_peak / t_meas,
             "ceiling_frac_of_peak": t_peak / t_ceil,
-            "body_frac_of_ceiling": t_ceil / t_body,
-            "tail_loss": 1.0 - t_body / t_meas,
+            "tail_loss": 1.0 - t_ceil / t_act,
+            "residual_frac": t_act / t_meas,
             "frac_of_ceiling": t_ceil / t_meas}
 
 

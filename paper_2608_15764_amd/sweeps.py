@@ -839,10 +839,11 @@ def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
                   vec_width=16):
     """Split the K sweep's distance from the datasheet figure into the part
     the design offers (cells whose bytes in flight over the HBM latency fall
-    below the datasheet), the tail loss of the static equal split (wave
-    slots idle inside the window, from one untimed launch per cell with its
-    per-wave clock records) and a residual.  ``summ`` is the timed sweep's
-    summary; its per-cell medians are the measured rates."""
+    below the datasheet), the tail loss of the static equal split (the
+    ceiling lost while only some waves still run, from one untimed launch
+    per cell with its per-wave clock records) and a residual.  ``summ`` is
+    the timed sweep's summary; its per-cell medians are the measured
+    rates."""
     dt = wave_rec_dtype()
     n_cus = isw.sweep_device_info()["num_cus"]
     rec = torch.zeros(n_cus * max(waves_list) * dt.itemsize, dtype=torch.uint8,
@@ -863,20 +864,15 @@ def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
             a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
             t0 = a["t0"].astype("int64").tolist()
             t1 = a["t1"].astype("int64").tolist()
-            # wave v handles groups v, v + n, ... below Q (round robin)
-            n, Q = r["waves"], r["issued_loads"] // (64 * K)
-            gb = 64 * K * vec_width
-            wb = [((Q - v + n - 1) // n) * gb for v in range(n)]
-            tl = stats.tail_loss(t0, t1, wb)
-            if tl is None:
-                tl = 0.0
+            per_wave = 64 * K * vec_width
             fl = stats.in_flight_bytes(r["waves"], K, vec_width)
             ceil = stats.littles_ceiling_gbps(fl, latency_ns)
+            act = stats.active_ceiling_gbps(t0, t1, per_wave, latency_ns)
             c = {"bytes": r["issued_bytes"], "gbps": g, "ceiling_gbps": ceil,
-                 "tail_loss": tl}
+                 "active_ceiling_gbps": act}
             cells.append(c)
             rows[K] = {"gbps": round(g, 1), "ceiling_gbps": round(ceil, 1),
-                       "body_gbps": round(g / (1.0 - tl), 1), "tail_loss": round(tl, 4),
+                       "active_ceiling_gbps": round(act, 1),
                        "idle_slots": round(stats.idle_slots(t0, t1), 4)}
         if rows:
             split = stats.gap_split([c for c in cells[-len(rows):]])
@@ -887,11 +883,10 @@ def gap_breakdown(buf, nbytes, L, policy, summ, latency_ns, waves_list, Ks,
     out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
     out["hbm_latency_ns"] = round(latency_ns, 1)
     out["by_waves_per_cu"] = per_w
-    out["method"] = ("ceiling = min(8 TB/s, bytes in flight / unloaded HBM latency); "
-                     "body rate = rate while every wave runs (all started, < 10 % "
-                     "finished), from one untimed launch per cell with per-wave clock "
-                     "records; tail loss = 1 - window rate / body rate; times summed "
-                     "over cells")
+    out["method"] = ("design ceiling = min(8 TB/s, bytes in flight of all waves / "
+                     "unloaded HBM latency); active ceiling = its time average with "
+                     "only the waves running at each moment, from one untimed launch "
+                     "per cell with per-wave clock records; times summed over cells")
     return out
 
 

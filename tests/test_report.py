@@ -61,7 +61,7 @@ def full_result():
                      "mean_launch_us": 161.7, "timing": "hipEvent pair per replay",
                      "algorithmic_bytes_per_launch": 1073739296},
         "gap": {"kernel_frac": 0.84, "ceiling_frac_of_peak": 0.98,
-                "frac_of_ceiling": 0.857, "tail_loss": 0.12, "body_frac_of_ceiling": 0.974,
+                "frac_of_ceiling": 0.857, "tail_loss": 0.12, "residual_frac": 0.974,
                 "hbm_latency_ns": 360.1, "by_waves_per_cu": {w: {} for w in curves}},
         "eager_sweep": {"step_ms": 42.0, "aggregate_gbps": 6442.0,
                         "dispatch_event_gbps": 6678.0},

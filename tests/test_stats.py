@@ -136,28 +136,33 @@ def test_front_duplicates_matches_brute_force():
         assert stats.front_duplicates(blocked, K, nw, Q, nv, max_iters=10**6) == dup / total
 
 
-def test_idle_slots_and_tail_loss_of_an_even_finish():
-    # every wave runs the whole window: nothing idle, nothing lost
-    t0, t1 = [0, 0, 0, 0], [100, 100, 100, 100]
-    assert stats.idle_slots(t0, t1) == 0.0
-    assert stats.tail_loss(t0, t1, [10] * 4) == 0.0
+def test_idle_slots():
+    # every wave runs the whole window: nothing idle
+    assert stats.idle_slots([0, 0, 0, 0], [100, 100, 100, 100]) == 0.0
+    # three of four waves stop at half time: 3 x 50 idle of 4 x 100
+    assert abs(stats.idle_slots([0, 0, 0, 0], [50, 50, 50, 100]) - 150 / 400) < 1e-12
+    assert stats.idle_slots([], []) == 0.0
 
 
-def test_tail_loss_of_an_uneven_finish():
-    """Four waves of 100 bytes each start together; three finish at t=50,
-    one at t=100.  While all run (0..50 at the 10 % quantile the first end
-    is at 50) the launch moves 2+2+2+1 = 7 bytes/tick; over its window it
-    moves 400/100 = 4 bytes/tick, so 1 - 4/7 of the body rate is lost."""
-    t0, t1 = [0, 0, 0, 0], [50, 50, 50, 100]
-    tl = stats.tail_loss(t0, t1, [100] * 4)
-    assert abs(tl - (1 - 4 / 7)) < 1e-12
-    # idle wave slots: 3 waves x 50 ticks of 4 x 100
-    assert abs(stats.idle_slots(t0, t1) - 150 / 400) < 1e-12
-    # a late starter: the body interval begins when the last wave starts
-    tl2 = stats.tail_loss([0, 0, 0, 20], [50, 50, 50, 100], [100] * 4)
-    assert tl2 is not None and 0 < tl2 < 1
-    assert stats.tail_loss([], [], []) is None
-    assert stats.tail_loss([0, 60], [50, 100], [1, 1], q=0.0) is None   # never all running
+def test_active_ceiling():
+    """Four waves of 1 MiB in flight each, latency 1000 ns (1 MiB / 1000 ns
+    = 1048.576 GB/s per wave).  All running all the time: the design
+    ceiling.  Three stopping at half time: half the window at 4 waves'
+    rate, half at one wave's."""
+    mib = float(1 << 20)
+    per = mib / 1000.0
+    full = stats.active_ceiling_gbps([0] * 4, [100] * 4, mib, 1000.0)
+    assert abs(full - 4 * per) < 1e-9
+    tail = stats.active_ceiling_gbps([0] * 4, [50, 50, 50, 100], mib, 1000.0)
+    assert abs(tail - (0.5 * 4 * per + 0.5 * per)) < 1e-9
+    # the datasheet caps every moment: a large offer loses nothing to the tail
+    # until too few waves remain to cover the bandwidth-delay product
+    capped = stats.active_ceiling_gbps([0] * 4, [50, 50, 50, 100], 64 * mib, 1000.0)
+    assert capped == stats.HBM_PEAK_GBPS
+    # a late start counts from the first start
+    late = stats.active_ceiling_gbps([0, 0, 0, 50], [100] * 4, mib, 1000.0)
+    assert abs(late - (0.5 * 3 * per + 0.5 * 4 * per)) < 1e-9
+    assert stats.active_ceiling_gbps([], [], mib, 1000.0) == 0.0
 
 
 def test_littles_ceiling():
@@ -168,19 +173,26 @@ def test_littles_ceiling():
 
 
 def test_gap_split_factors_multiply_to_the_kernel_fraction():
-    cells = [{"bytes": 1e9, "gbps": 2000.0, "ceiling_gbps": 2900.0, "tail_loss": 0.05},
-             {"bytes": 1e9, "gbps": 7000.0, "ceiling_gbps": 8000.0, "tail_loss": 0.10},
-             {"bytes": 2e9, "gbps": 6800.0, "ceiling_gbps": 8000.0, "tail_loss": 0.20}]
+    cells = [{"bytes": 1e9, "gbps": 2000.0, "ceiling_gbps": 2900.0,
+              "active_ceiling_gbps": 2700.0},
+             {"bytes": 1e9, "gbps": 7000.0, "ceiling_gbps": 8000.0,
+              "active_ceiling_gbps": 8000.0},
+             {"bytes": 2e9, "gbps": 6800.0, "ceiling_gbps": 8000.0,
+              "active_ceiling_gbps": 7600.0}]
     g = stats.gap_split(cells)
     t_meas = 1e9 / 2000 + 1e9 / 7000 + 2e9 / 6800
     assert abs(g["kernel_frac"] - (4e9 / 8000) / t_meas) < 1e-12
-    prod = g["ceiling_frac_of_peak"] * g["body_frac_of_ceiling"] * (1 - g["tail_loss"])
+    prod = g["ceiling_frac_of_peak"] * (1 - g["tail_loss"]) * g["residual_frac"]
     assert abs(prod - g["kernel_frac"]) < 1e-12
-    assert abs(g["frac_of_ceiling"] - g["body_frac_of_ceiling"] * (1 - g["tail_loss"])) < 1e-12
-    # every cell at its ceiling, no tail: all factors but the design one are 1
-    flat = [dict(c, gbps=c["ceiling_gbps"], tail_loss=0.0) for c in cells]
+    t_ceil = 1e9 / 2900 + 1e9 / 8000 + 2e9 / 8000
+    t_act = 1e9 / 2700 + 1e9 / 8000 + 2e9 / 7600
+    assert abs(g["tail_loss"] - (1 - t_ceil / t_act)) < 1e-12
+    assert abs(g["residual_frac"] - t_act / t_meas) < 1e-12
+    # every cell at its ceiling with no tail: only the design factor is left
+    flat = [dict(c, gbps=c["ceiling_gbps"], active_ceiling_gbps=c["ceiling_gbps"])
+            for c in cells]
     g = stats.gap_split(flat)
-    assert abs(g["body_frac_of_ceiling"] - 1) < 1e-12 and abs(g["tail_loss"]) < 1e-12
+    assert abs(g["residual_frac"] - 1) < 1e-12 and abs(g["tail_loss"]) < 1e-12
     assert abs(g["kernel_frac"] - g["ceiling_frac_of_peak"]) < 1e-12
     with pytest.raises(ValueError):
         stats.gap_split([])
