@@ -249,6 +249,29 @@ int sweep_plain(const void* buf, size_t bytes, int K, int vec_width,
                 int waves_per_cu, uint64_t total_logical_loads,
                 const sweep_opts_t* opt, sweep_result_t* out);
 
+/* sweep_plain for callers that cannot allocate memory (code that must not
+ * call hipMalloc: tight serving or measurement loops, harnesses that forbid
+ * allocation).  Same arguments, kernels, validation and results as
+ * sweep_plain, except:
+ *  - The wave records, the cell result and the record offsets live in a
+ *    static device array of 512 KiB + 256 bytes per GPU, held until the
+ *    process ends; the call allocates nothing (no hipMalloc, hipFree, pinned
+ *    host memory or events).  Its device address is resolved once per GPU,
+ *    in sweep_init() or else on the first call on that GPU.
+ *  - A launch of more than 16384 waves (CUs * waves_per_cu) fails with
+ *    SWEEP_EINVAL unless opt->wave_out receives the records instead.
+ *  - event_ms is 0: the call is timed by the kernel's own clock window
+ *    (window_ns, gbps) and returns after a stream synchronisation.
+ *  - Every call on a GPU shares that GPU's array, which keeps the last
+ *    call's contents; each call writes everything it reads before reading
+ *    it.  Calls take the library lock and return only when their work is
+ *    done, so calls from one process do not overlap; work that overlapped
+ *    it on the same GPU from outside the library would race on the array.
+ * Errors: as sweep_plain. */
+int sweep_plain_noalloc(const void* buf, size_t bytes, int K, int vec_width,
+                        int waves_per_cu, uint64_t total_logical_loads,
+                        const sweep_opts_t* opt, sweep_result_t* out);
+
 /* LDS-direct asynchronous path (Section 4.3, the counterpart of cp.async:
  * loads that write LDS with no destination register).  Every wave keeps a
  * ring of `depth` 1 KiB LDS slots; each slot is filled by one

@@ -88,6 +88,17 @@ struct CellRes {
   uint64_t tmax;
 };
 
+// ---- static scratch of the allocation-free entry point (static_scratch.hip)
+// Layout: per-wave records, then the cell result, then the two record
+// offsets the finishing kernel reads.  512 KiB + 256 bytes per device.
+constexpr uint64_t kStaticRecords = 16384;
+constexpr uint64_t kStaticResOffset = kStaticRecords * sizeof(sweep_wave_rec_t);
+constexpr uint64_t kStaticOffsOffset = kStaticResOffset + 64;
+constexpr uint64_t kStaticScratchBytes = kStaticResOffset + 256;
+// Device address of the calling thread's current device's copy of the
+// static scratch (resolved once per device, with that device current).
+hipError_t static_scratch(int ordinal, uint8_t** ptr);
+
 // ---- kernel lookup: the host launches these with their one argument
 // struct (PlainArgs, LdsArgs, TwoStreamArgs, ReduceArgs); nullptr for an
 // unknown combination.

@@ -75,6 +75,7 @@ struct Dev {
     int max_wgs;
   };
   std::map<std::tuple<const void*, uint32_t, size_t>, Occ> occ;
+  bool scratch_ready = false;   // setup_device has run
   double hz() const { return cal_hz > 0 ? cal_hz : nominal_hz; }
 };
 
@@ -149,13 +150,19 @@ int setup_device(Dev* d) {
   size_t chase_cap = 0;
   SW_TRY(ensure_dev(d->chase_out, chase_cap, 5));
   SW_TRY(ensure_events(*d, 8));
+  d->scratch_ready = true;
   return SWEEP_OK;
 }
 
-int init_device(int ordinal, Dev** out) {
+// The device's state: its properties always; its library-owned scratch and
+// events too when `alloc` is set (every entry point but the allocation-free
+// one).
+int init_device(int ordinal, Dev** out, bool alloc = true) {
   auto it = g_devs.find(ordinal);
   if (it != g_devs.end()) {
-    *out = it->second;
+    Dev* d = it->second;
+    if (alloc && !d->scratch_ready) SW_TRY(setup_device(d));
+    *out = d;
     return SWEEP_OK;
   }
   hipDeviceProp_t prop;
@@ -177,7 +184,7 @@ int init_device(int ordinal, Dev** out) {
   d->mem_khz = prop.memoryClockRate;
   d->bus_bits = prop.memoryBusWidth;
   d->nominal_hz = wc_khz > 0 ? wc_khz * 1000.0 : 1.0e8;
-  const int rc = setup_device(d);
+  const int rc = alloc ? setup_device(d) : SWEEP_OK;
   if (rc != SWEEP_OK) {
     release_device(d);
     return rc;
@@ -187,10 +194,10 @@ int init_device(int ordinal, Dev** out) {
   return SWEEP_OK;
 }
 
-int current_dev(Dev** out) {
+int current_dev(Dev** out, bool alloc = true) {
   int ord = 0;
   HIP_TRY(hipGetDevice(&ord));
-  return init_device(ord, out);
+  return init_device(ord, out, alloc);
 }
 
 // ----------------------------------------------------------- cell prep
@@ -204,7 +211,10 @@ struct Prepared {
   hipFuncAttributes fa{};
 };
 
-int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
+// Plans and checks a cell.  With `cache` the kernel's attributes and
+// residency limit are kept per device; without, they are queried afresh
+// (the allocation-free entry point keeps no state of its own).
+int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out, bool cache = true) {
   PlanIn in;
   in.bytes = c.bytes;
   in.K = c.K;
@@ -238,17 +248,19 @@ int prepare(Dev& d, const sweep_cell_t& c, int pin, Prepared* out) {
     return fail(SWEEP_EINVAL, "plain cells run 256-thread workgroups");
   p.lds = p.plan.lds_ring_bytes;
   if (pin && p.plan.pub.lds_pad_bytes > p.lds) p.lds = p.plan.pub.lds_pad_bytes;
+  Dev::Occ o;
   const auto key = std::make_tuple(p.fn, p.threads, p.lds);
   auto it = d.occ.find(key);
-  if (it == d.occ.end()) {
-    Dev::Occ o;
+  if (it != d.occ.end()) {
+    o = it->second;
+  } else {
     HIP_TRY(hipFuncGetAttributes(&o.fa, p.fn));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o.max_wgs, p.fn, (int)p.threads,
                                                          p.lds));
-    it = d.occ.emplace(key, o).first;
+    if (cache) d.occ.emplace(key, o);
   }
-  p.fa = it->second.fa;
-  const int nb = it->second.max_wgs;
+  p.fa = o.fa;
+  const int nb = o.max_wgs;
   p.max_wgs = nb;
   if ((uint32_t)nb < p.plan.wgs_per_cu)
     return fail(SWEEP_EOCCUPANCY,
@@ -532,7 +544,11 @@ int sweep_init(int ordinal) {
   if (ordinal < 0 || ordinal >= n) return fail(SWEEP_ENODEV, "no such device");
   HIP_TRY(hipSetDevice(ordinal));
   Dev* d = nullptr;
-  return init_device(ordinal, &d);
+  SW_TRY(init_device(ordinal, &d));
+  // the allocation-free entry point's static scratch on this device
+  uint8_t* sp = nullptr;
+  HIP_TRY(static_scratch(ordinal, &sp));
+  return SWEEP_OK;
 }
 
 int sweep_shutdown(void) {
@@ -701,6 +717,41 @@ int sweep_run(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
   std::vector<Prepared> ps((size_t)n);
   for (int i = 0; i < n; ++i) SW_TRY(prepare(*d, cells[i], pin_of(opt), &ps[(size_t)i]));
   return run_prepared(*d, ps, as_stream(opt), nullptr, nullptr, results);
+}
+
+int sweep_plain_noalloc(const void* buf, size_t bytes, int K, int vec_width,
+                        int waves_per_cu, uint64_t total_logical_loads,
+                        const sweep_opts_t* opt, sweep_result_t* out) {
+  if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d, false));
+  uint8_t* sp = nullptr;
+  HIP_TRY(static_scratch(d->ordinal, &sp));
+  Prepared p;
+  SW_TRY(prepare(*d, cell_from(SWEEP_KIND_PLAIN, buf, bytes, K, vec_width, waves_per_cu,
+                               total_logical_loads, opt),
+                 pin_of(opt), &p, false));
+  const uint64_t waves = p.plan.pub.waves;
+  SW_TRY(check_outputs(opt, waves));
+  sweep_wave_rec_t* wave_out = opt ? opt->wave_out : nullptr;
+  if (!wave_out && waves > kStaticRecords)
+    return fail(SWEEP_EINVAL, "the launch's waves exceed the static scratch (16384 records)");
+  sweep_wave_rec_t* rec = wave_out ? wave_out : reinterpret_cast<sweep_wave_rec_t*>(sp);
+  CellRes* res = reinterpret_cast<CellRes*>(sp + kStaticResOffset);
+  uint64_t* offs = reinterpret_cast<uint64_t*>(sp + kStaticOffsOffset);
+  hipStream_t st = as_stream(opt);
+  // every value the kernels read is written first in this call: the record
+  // offsets here, the records by the sweep kernel, the result by the finish
+  const uint64_t offs_h[2] = {0, waves};
+  CellRes r;
+  HIP_TRY(hipMemcpyAsync(offs, offs_h, sizeof(offs_h), hipMemcpyHostToDevice, st));
+  HIP_TRY(enqueue(p, st, rec, opt ? opt->lane_out : nullptr, nullptr, nullptr));
+  HIP_TRY(launch_finish_cells(rec, offs, 1, res, st));
+  HIP_TRY(hipMemcpyAsync(&r, res, sizeof(r), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  fill_result(*d, p, r, 0.0, out);
+  return SWEEP_OK;
 }
 
 }  // extern "C"

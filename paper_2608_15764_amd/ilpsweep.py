@@ -113,6 +113,9 @@ _SIG = {
     "sweep_plain": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
                               C.c_uint64, C.POINTER(sweep_opts_t),
                               C.POINTER(sweep_result_t)]),
+    "sweep_plain_noalloc": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                      C.c_uint64, C.POINTER(sweep_opts_t),
+                                      C.POINTER(sweep_result_t)]),
     "sweep_lds_async": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_int, C.c_int,
                                   C.c_uint64, C.POINTER(sweep_opts_t),
                                   C.POINTER(sweep_result_t)]),
@@ -289,6 +292,12 @@ def _cell_call(fn, name, buf, bytes_, K, vec_width, waves_per_cu, L, opts):
 def sweep_plain(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
                 opts=None):
     return _cell_call(lib.sweep_plain, "sweep_plain", buf, bytes_, K,
+                      vec_width, waves_per_cu, total_logical_loads, opts)
+
+
+def sweep_plain_noalloc(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
+                        opts=None):
+    return _cell_call(lib.sweep_plain_noalloc, "sweep_plain_noalloc", buf, bytes_, K,
                       vec_width, waves_per_cu, total_logical_loads, opts)
 
 
