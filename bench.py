@@ -530,7 +530,7 @@ def main():
                         "gpu_before": env_before, "gpu_after": env_after},
     }
     # the strict .cg analogue, timed like the headline
-    if a.policy != "bypass_l1":
+    if a.policy != "bypass_l1" and not a.no_extras:
         result["strict_cg"] = strict_cg_sweep(a, isw, sweeps, stats, buf, nbytes, L,
                                               waves_list, Ks)
     # the same sweep launched eagerly, cell by cell (sweep_run): the cost of
