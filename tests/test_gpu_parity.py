@@ -573,6 +573,51 @@ def test_sweep_drivers_run_small():
     assert sg["best_gbps"] >= sg["median_gbps"] > 0
 
 
+def test_new_bench_rows_run_small():
+    """The rows added to the benchmark, on small inputs: the gate's verdict,
+    the gap split, the regime map on several backends, coverage in the
+    order/footprint and allocation rows, and the oracle-checked batch."""
+    from oracle import checksums
+    from paper_2608_15764_amd import stats, sweeps
+    nbytes = 8 << 20
+    buf = sweeps.device_buffer(nbytes, 13)
+    sg = sweeps.streaming_gate(buf, nbytes, launches=3, latency_ns=360.0)
+    assert sg["verdict"] in ("pass", "latency-bound", "fail")
+    assert sg["littles_law_ceiling_gbps"] == pytest.approx(
+        stats.littles_ceiling_gbps(sg["in_flight_bytes"], 360.0))
+    Ks, waves = [1, 2, 4], [4, 16]
+    summ = sweeps.plain_k_sweep(buf, nbytes, nbytes // 16, isw.CACHE_BYPASS_L1_NT, waves, Ks,
+                                passes=2)
+    gap = sweeps.gap_breakdown(buf, nbytes, nbytes // 16, isw.CACHE_BYPASS_L1_NT, summ, 360.0,
+                               waves, Ks)
+    prod = gap["ceiling_frac_of_peak"] * (1 - gap["tail_loss"]) * gap["residual_frac"]
+    assert prod == pytest.approx(gap["kernel_frac"], rel=1e-3)
+    assert set(gap["by_waves_per_cu"]) == set(waves)
+    for row in gap["by_waves_per_cu"].values():
+        for c in row["cells"].values():
+            assert 0 < c["active_ceiling_gbps"] <= c["ceiling_gbps"] + 1e-6
+    rm = sweeps.regime_map(waves_list=(4, 8), widths=(16,), Ks=range(1, 5),
+                           backends=(("a", 4 << 20), ("b", 2 << 20)), work_bytes=8 << 20, n=1)
+    assert set(rm["backends"]) == {"a", "b"}
+    for b in rm["backends"].values():
+        assert sum(b["counts"].values()) == 4 and b["launches_per_cell"] == 2
+    of = sweeps.order_footprint([1 << 20, 4 << 20], Ks=(1, 2), L=1 << 17, n=1)
+    assert of[4 << 20]["blocked"]["coverage"][2]["coverage"] == 0.5
+    assert of[1 << 20]["round_robin"]["coverage"][1]["max_reads"] == 2
+    seen = []
+
+    def verify(checks):
+        seen.extend(checks)
+        want = checksums.range_sinks_many([c[:3] for c in checks], threads=4)
+        return [w == (c[3], c[4]) for w, c in zip(want, checks)]
+
+    space = {"vec_widths": [4, 16], "Ks": [3, 7], "waves_per_cu": [4, 12],
+             "policies": [isw.CACHE_NT]}
+    bt = sweeps.batched_autotuned(n_points=6, n=2, space=space, verify=verify, hi_log2=24)
+    assert bt["matches_oracle"] and bt["points_checked"] == 12 == len(seen)
+    assert bt["batched_aggregate_gbps"] > 0
+
+
 def test_graph_replays_match_eager_runs():
     """Several graph launches with eager work and synchronisation between
     them; every replay must reproduce the eager sinks."""
