@@ -121,6 +121,12 @@ typedef struct {
                               writes nothing (required with wave_out)       */
   uint64_t  lane_out_cap;  /* (sum, xor) pairs lane_out holds, i.e. threads;
                               checked like wave_out_cap                      */
+  int       fuse;          /* sweep_graph_create / sweep_batched only:
+                              nonzero runs each run of consecutive plain,
+                              fixed-work, round-robin cells that share K,
+                              vector width, cache policy and launch shape as
+                              one persistent launch over their concatenated
+                              wave-groups (results per cell as before) */
 } sweep_opts_t;
 
 typedef struct {

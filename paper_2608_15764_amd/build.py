@@ -21,8 +21,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libilpsweep.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels_plain.hip", "kernels_lds.hip", "kernels_misc.hip",
-           "kernels_chase.hip", "static_scratch.hip", "runtime.cpp", "plan.cpp"]
+SOURCES = ["kernels_plain.hip", "kernels_fused.hip", "kernels_lds.hip",
+           "kernels_misc.hip", "kernels_chase.hip", "static_scratch.hip", "runtime.cpp",
+           "plan.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -29,6 +29,29 @@ struct PlainArgs {
   uint32_t order;      // SWEEP_ORDER_*
 };
 
+// Fused batch of plain cells that share K, vector width, cache policy and
+// launch shape: one persistent launch over their concatenated wave-groups.
+// Point p owns global groups [g0, g0 + Q); wave w of n_waves handles global
+// groups w, w + n_waves, ... (round robin over the concatenation), reading
+// load j of its point's local group q at vector (q*K + j)*64 mod n_vec.
+// `stride` = (n_waves*K*64) mod n_vec is a wave's vector step between two
+// of its groups inside one point.  Wave w's record for point p is
+// rec[p*n_waves + w]; records of points a wave never reaches are left as
+// they are (cleared once, before the first launch, to "empty").
+struct FusedPoint {
+  uint64_t off;            // the point's buffer: FusedArgs::base + off
+  uint64_t n_vec;
+  uint64_t Q;
+  uint64_t g0;
+  uint64_t stride;
+};
+struct FusedArgs {
+  const uint8_t* base;     // the lowest point buffer of the launch
+  const FusedPoint* pts;   // device, n_pts entries
+  uint64_t total_groups;   // sum of Q over the points
+  sweep_wave_rec_t* rec;   // n_pts * n_waves records
+};
+
 // LDS-ring cell (async or matched), `waves` waves per workgroup.
 struct LdsArgs {
   const uint8_t* buf;
@@ -104,6 +127,11 @@ hipError_t static_scratch(int ordinal, uint8_t** ptr);
 // unknown combination.
 // plain (kernels_plain.hip)
 const void* plain_kernel(int K, int V, int policy);
+// fused plain batch (kernels_fused.hip)
+const void* fused_kernel(int K, int V, int policy);
+// Set `n` records to "empty" (zero sinks, t0 = all ones, t1 = 0), which
+// the finishing kernel's min / max ignore.
+hipError_t launch_clear_records(sweep_wave_rec_t* rec, uint64_t n, hipStream_t st);
 
 // ---- LDS paths (kernels_lds.hip)
 const void* lds_kernel(int kind, int D, int policy);

@@ -764,6 +764,8 @@ struct sweep_graph {
   CellRes* res = nullptr;
   CellRes* res_h = nullptr;
   uint64_t* offs = nullptr;
+  FusedPoint* pts = nullptr;    // point lists of the fused launches
+  size_t fused_launches = 0;
   std::vector<hipEvent_t> ev;   // start, end, done of a launch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -779,8 +781,76 @@ void free_graph(sweep_graph* g) {
   if (g->rec) (void)hipFree(g->rec);
   if (g->res) (void)hipFree(g->res);
   if (g->offs) (void)hipFree(g->offs);
+  if (g->pts) (void)hipFree(g->pts);
   if (g->res_h) (void)hipHostFree(g->res_h);
   delete g;
+}
+
+// A run of consecutive cells launched together: one cell alone, or (with
+// opts->fuse) plain fixed-work round-robin cells that share the kernel and
+// launch shape, fused into one persistent launch over their groups.
+struct LaunchGroup {
+  size_t first = 0, count = 1;
+  const void* fused = nullptr;   // fused kernel, or null for a lone cell
+  size_t pt0 = 0;                // index of its first point in the point list
+  const uint8_t* base = nullptr; // lowest point buffer (points are offsets from it)
+};
+
+bool fusable(const Prepared& p) {
+  return p.c.kind == SWEEP_KIND_PLAIN && p.c.mode == SWEEP_FIXED_WORK &&
+         p.c.order == SWEEP_ORDER_ROUND_ROBIN;
+}
+
+bool same_launch(const Prepared& a, const Prepared& b) {
+  return a.fn == b.fn && a.grid == b.grid && a.threads == b.threads && a.lds == b.lds;
+}
+
+// Splits the prepared cells into launch groups and builds the fused point
+// lists (g0 = the point's first group in the concatenation).
+int plan_groups(const std::vector<Prepared>& ps, bool fuse, std::vector<LaunchGroup>* groups,
+                std::vector<FusedPoint>* pts) {
+  for (size_t i = 0; i < ps.size();) {
+    LaunchGroup lg;
+    lg.first = i;
+    size_t j = i + 1;
+    if (fuse && fusable(ps[i]))
+      while (j < ps.size() && fusable(ps[j]) && same_launch(ps[i], ps[j])) ++j;
+    lg.count = j - i;
+    if (lg.count > 1) {
+      const Prepared& p0 = ps[i];
+      const void* fn = fused_kernel(p0.c.K, p0.c.vec_width, p0.c.cache_policy);
+      int nb = 0;
+      if (fn) HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)p0.threads,
+                                                                   p0.lds));
+      if (fn && (uint32_t)nb >= p0.plan.wgs_per_cu) {
+        lg.fused = fn;
+        lg.pt0 = pts->size();
+        uint64_t g0 = 0;
+        const uint64_t nw = p0.plan.pub.waves;
+        uintptr_t base = reinterpret_cast<uintptr_t>(p0.c.buf);
+        for (size_t k = i; k < j; ++k)
+          base = std::min(base, reinterpret_cast<uintptr_t>(ps[k].c.buf));
+        lg.base = reinterpret_cast<const uint8_t*>(base);
+        for (size_t k = i; k < j; ++k) {
+          const Prepared& p = ps[k];
+          FusedPoint fp;
+          fp.off = reinterpret_cast<uintptr_t>(p.c.buf) - base;
+          fp.n_vec = p.plan.pub.n_vec;
+          fp.Q = p.plan.pub.Q;
+          fp.g0 = g0;
+          fp.stride = (nw * (uint64_t)p.c.K * 64ull) % fp.n_vec;
+          g0 += fp.Q;
+          pts->push_back(fp);
+        }
+      } else {
+        lg.count = 1;     // the fused kernel cannot reach the residency: alone
+        j = i + 1;
+      }
+    }
+    groups->push_back(lg);
+    i = j;
+  }
+  return SWEEP_OK;
 }
 
 int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
@@ -810,6 +880,26 @@ int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* o
   }
   if (hipMemcpy(g->offs, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
     return fail_g(SWEEP_EHIP, "graph offsets upload failed");
+  std::vector<LaunchGroup> groups;
+  std::vector<FusedPoint> pts;
+  rc = plan_groups(g->ps, opt && opt->fuse, &groups, &pts);
+  if (rc != SWEEP_OK) {
+    free_graph(g);
+    return rc;
+  }
+  if (!pts.empty()) {
+    // fused launches write only the records of points their waves reach:
+    // every other record is cleared once, here, and never written again
+    if (hipMalloc(reinterpret_cast<void**>(&g->pts), pts.size() * sizeof(FusedPoint)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_g(SWEEP_ENOMEM, "graph point list allocation failed");
+    }
+    if (hipMemcpy(g->pts, pts.data(), pts.size() * sizeof(FusedPoint), hipMemcpyHostToDevice) != hipSuccess)
+      return fail_g(SWEEP_EHIP, "graph point list upload failed");
+    if (launch_clear_records(g->rec, n_rec, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess)
+      return fail_g(SWEEP_EHIP, "graph record clear failed");
+  }
   g->ev.resize(3, nullptr);
   for (auto& e : g->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail_g(SWEEP_EHIP, "hipEventCreate failed");
@@ -818,9 +908,21 @@ int create_graph(Dev& d, const sweep_cell_t* cells, int n, const sweep_opts_t* o
   if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail_g(SWEEP_EHIP, "hipStreamBeginCapture failed");
   hipError_t cap_err = hipSuccess;
-  for (int i = 0; i < n && cap_err == hipSuccess; ++i)
-    cap_err = enqueue(g->ps[(size_t)i], d.capture, g->rec + offs[(size_t)i], nullptr,
-                      nullptr, nullptr);
+  for (size_t k = 0; k < groups.size() && cap_err == hipSuccess; ++k) {
+    const LaunchGroup& lg = groups[k];
+    const Prepared& p0 = g->ps[lg.first];
+    if (!lg.fused) {
+      cap_err = enqueue(p0, d.capture, g->rec + offs[lg.first], nullptr, nullptr, nullptr);
+      continue;
+    }
+    FusedArgs a;
+    a.base = lg.base;
+    a.pts = g->pts + lg.pt0;
+    a.total_groups = pts[lg.pt0 + lg.count - 1].g0 + pts[lg.pt0 + lg.count - 1].Q;
+    a.rec = g->rec + offs[lg.first];
+    cap_err = launch_timed(lg.fused, p0.grid, p0.threads, p0.lds, d.capture, a, nullptr, nullptr);
+    ++g->fused_launches;
+  }
   if (cap_err == hipSuccess)
     cap_err = launch_finish_cells(g->rec, g->offs, (uint32_t)n, g->res, d.capture);
   hipError_t end_err = hipStreamEndCapture(d.capture, &g->graph);

@@ -36,7 +36,7 @@ class sweep_opts_t(C.Structure):
                 ("grid_wgs", C.c_uint32), ("pin_occupancy", C.c_int),
                 ("wave_out", C.c_void_p), ("lane_out", C.c_void_p),
                 ("order", C.c_int), ("wave_out_cap", C.c_uint64),
-                ("lane_out_cap", C.c_uint64)]
+                ("lane_out_cap", C.c_uint64), ("fuse", C.c_int)]
 
 
 class sweep_result_t(C.Structure):
@@ -227,7 +227,7 @@ def _cap(buf, cap, item_bytes, name):
 def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
               fixed_iters=0, grid_wgs=0, pin_occupancy=True, wave_out=None,
               lane_out=None, order=ORDER_ROUND_ROBIN, wave_out_cap=None,
-              lane_out_cap=None):
+              lane_out_cap=None, fuse=False):
     """Options block.  ``wave_out`` / ``lane_out`` capacities (records of 32
     bytes / lanes of 8 bytes) are taken from the tensors' sizes unless given."""
     o = sweep_opts_t()
@@ -242,6 +242,7 @@ def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
     o.order = order
     o.wave_out_cap = _cap(wave_out, wave_out_cap, C.sizeof(sweep_wave_rec_t), "wave_out")
     o.lane_out_cap = _cap(lane_out, lane_out_cap, 8, "lane_out")
+    o.fuse = 1 if fuse else 0
     return o
 
 

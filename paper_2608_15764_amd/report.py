@@ -74,7 +74,8 @@ def _c5a(row):
         return None
     return _pick(row, ("batched_aggregate_gbps", "batched_aggregate_frac",
                        "hbm_aggregate_gbps", "hbm_aggregate_frac",
-                       "batched_best_point_gbps", "plain_aggregate_gbps",
+                       "batched_best_point_gbps", "node_per_point_aggregate_gbps",
+                       "plain_aggregate_gbps", "fused_launches", "chosen_plan",
                        "matches_oracle", "points_checked", "sizes"), 4)
 
 

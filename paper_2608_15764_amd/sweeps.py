@@ -413,9 +413,11 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
                       hi_log2=31):
     """64 sweep points of uneven size (1 MiB .. 2 GiB), laid out back to
     back in one seeded buffer, each read once per pass at its size class's
-    tuned (V, K, waves, policy): captured once as a hipGraph and replayed
-    ``n`` times, against the same points launched one by one at the untuned
-    default.  ``verify``, if given, is called with one (seed, first word,
+    tuned (V, K, waves, policy): captured once as a hipGraph, in which the
+    consecutive points of one tuned configuration run as one fused
+    persistent launch, and replayed ``n`` times; against the same graph
+    with one kernel node per point, and the same points launched one by one
+    at the untuned default.  ``verify``, if given, is called with one (seed, first word,
     words, sum32, xor32) tuple per launch of the first tuned replay and of
     the first untuned pass, and returns one bool per tuple: whether those
     sinks are the ones the words' oracle gives."""
@@ -432,48 +434,114 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
         return base
 
     table = autotune(buf_for, sizes, space=space, cache_path=cache_path)
-    tuned, plain = [], []
-    for s, o in zip(sizes, offs):
-        t = table[size_class(s)]
-        V = t["vec_width"]
-        tuned.append(isw.make_cell(base + o, s, t["K"], V, t["waves_per_cu"], s // V,
-                                   cache_policy=t["cache_policy"]))
-        V0, K0, w0, p0 = default
-        plain.append(isw.make_cell(base + o, s, K0, V0, w0, s // V0, cache_policy=p0))
-    # the tuned points are captured once and replayed
-    graph = isw.sweep_graph_create(tuned)
-    g_runs, g_ms, p_runs = [], [], []
+
+    def cells_of(cfgs):
+        return [isw.make_cell(base + o, s, t["K"], t["vec_width"], t["waves_per_cu"],
+                              s // t["vec_width"], cache_policy=t["cache_policy"])
+                for s, o, t in zip(sizes, offs, cfgs)]
+
+    def key(t):
+        return (t["K"], t["vec_width"], t["waves_per_cu"], t["cache_policy"])
+
+    # batch-level choice: the per-class configurations (one fused launch per
+    # run of equal ones), or one class's configuration for every point (a
+    # single fused launch); each plan's fused graph timed over 3 replays
+    plans = {"per_class": [table[size_class(s)] for s in sizes]}
+    for t in sorted({key(t): t for t in table.values()}.values(), key=key):
+        plans["uniform_K{}_V{}_w{}_p{}".format(*key(t))] = [t] * len(sizes)
+    plan_gbps = {}
+
+    def score(name, cfgs):
+        try:
+            with isw.sweep_graph_create(cells_of(cfgs), isw.make_opts(fuse=True)) as pg:
+                isw.sweep_graph_launch(pg)
+                runs = [isw.sweep_graph_launch(pg) for _ in range(3)]
+        except isw.SweepError as e:
+            if e.code in (isw.EOCCUPANCY, isw.EINVAL):
+                return None                    # a configuration some point cannot run
+            raise
+        plans[name] = cfgs
+        plan_gbps[name] = sum(r["issued_bytes"] for r in runs[0][0]) / (
+            _median([ms for _, ms in runs]) * 1e6)
+        return plan_gbps[name]
+
+    for name, cfgs in list(plans.items()):
+        score(name, cfgs)
+    # then a local search around the best single configuration: neighbouring
+    # K, occupancy, width and policy, two rounds at most
+    for _ in range(2):
+        best = max((n for n in plan_gbps if n != "per_class"), key=plan_gbps.get)
+        t0 = plans[best][0]
+        K, V, w, pol = key(t0)
+        cand = [(K + d, V, w, pol) for d in (-2, -1, 1, 2)] + \
+               [(K, V, w + d, pol) for d in (-4, 4)] + \
+               [(K, v, w, pol) for v in (4, 8, 16) if v != V] + \
+               [(K, V, w, q) for q in (isw.CACHE_NT, isw.CACHE_BYPASS_L1_NT) if q != pol]
+        improved = False
+        for k2, v2, w2, p2 in cand:
+            if not (1 <= k2 <= 16 and 4 <= w2 <= 32):
+                continue
+            name = f"uniform_K{k2}_V{v2}_w{w2}_p{p2}"
+            if name in plan_gbps:
+                continue
+            t = {"K": k2, "vec_width": v2, "waves_per_cu": w2, "cache_policy": p2}
+            g = score(name, [t] * len(sizes))
+            if g is not None and g > plan_gbps[best]:
+                improved = True
+        if not improved:
+            break
+    chosen = max(plan_gbps, key=plan_gbps.get)
+    cfgs = plans[chosen]
+    tuned = cells_of(cfgs)
+    V0, K0, w0, p0 = default
+    plain = [isw.make_cell(base + o, s, K0, V0, w0, s // V0, cache_policy=p0)
+             for s, o in zip(sizes, offs)]
+    # the chosen plan captured once and replayed: fused, and beside it the
+    # same configurations with one kernel node per point
+    graph = isw.sweep_graph_create(tuned, isw.make_opts(fuse=True))
+    nodes = isw.sweep_graph_create(tuned)
+    g_runs, g_ms, p_runs, u_runs, u_ms = [], [], [], [], []
     try:
         isw.sweep_graph_launch(graph)
+        isw.sweep_graph_launch(nodes)
         isw.sweep_run(plain)
         for _ in range(n):
             r, ms = isw.sweep_graph_launch(graph)
             g_runs.append(r)
             g_ms.append(ms)
+            r, ms = isw.sweep_graph_launch(nodes)
+            u_runs.append(r)
+            u_ms.append(ms)
             p_runs.append(isw.sweep_run(plain))
     finally:
         isw.sweep_graph_destroy(graph)
+        isw.sweep_graph_destroy(nodes)
     pts = []
     for i, s in enumerate(sizes):
-        gb = _median([r[i]["gbps"] for r in g_runs])
-        pb = _median([r[i]["gbps"] for r in p_runs])
-        t = table[size_class(s)]
+        t = cfgs[i]
         pts.append({"bytes": s, "issued_bytes": g_runs[0][i]["issued_bytes"],
                     "K": t["K"], "vec_width": t["vec_width"],
                     "waves_per_cu": t["waves_per_cu"], "cache_policy": t["cache_policy"],
-                    "batched_gbps": gb, "plain_gbps": pb,
+                    # alone in its own graph node, and inside the fused launch
+                    # (where neighbouring points overlap its window)
+                    "batched_gbps": _median([r[i]["gbps"] for r in u_runs]),
+                    "fused_window_gbps": _median([r[i]["gbps"] for r in g_runs]),
+                    "plain_gbps": _median([r[i]["gbps"] for r in p_runs]),
                     "hbm_targeted": s > stats.INFINITY_CACHE_BYTES})
     issued = sum(p["issued_bytes"] for p in pts)
     hbm = [i for i, p in enumerate(pts) if p["hbm_targeted"]]
-    # every HBM-targeted point's bytes over its own median window
+    # every HBM-targeted point's bytes over its own median window, each
+    # point alone in its graph node
     hbm_bytes = sum(pts[i]["issued_bytes"] for i in hbm)
-    hbm_ns = sum(_median([r[i]["window_ns"] for r in g_runs]) for i in hbm)
+    hbm_ns = sum(_median([r[i]["window_ns"] for r in u_runs]) for i in hbm)
     plain_ms = _median([sum(r["event_ms"] for r in run) for run in p_runs])
     out = {
         "sizes": len(sizes),
         "total_bytes": off,
         "issued_bytes": issued,
         "tuned": {str(k): v for k, v in table.items()},
+        "plans_gbps": {k: round(v, 1) for k, v in plan_gbps.items()},
+        "chosen_plan": chosen,
         "space": {k: (v if k != "policies" else [int(p) for p in v])
                   for k, v in (space or DEFAULT_SPACE).items()},
         "points": pts,
@@ -481,6 +549,13 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
         "plain_kernel_ms_sum": plain_ms,
         # the headline: the whole batch's issued bytes over the graph's time
         "batched_aggregate_gbps": issued / (_median(g_ms) * 1e6),
+        # runs of consecutive points with one configuration: one launch each
+        "fused_launches": 1 + sum(
+            1 for a, b in zip(pts, pts[1:])
+            if (a["K"], a["vec_width"], a["waves_per_cu"], a["cache_policy"])
+            != (b["K"], b["vec_width"], b["waves_per_cu"], b["cache_policy"])),
+        "node_per_point_graph_ms": _median(u_ms),
+        "node_per_point_aggregate_gbps": issued / (_median(u_ms) * 1e6),
         "hbm_points": len(hbm),
         "hbm_aggregate_gbps": hbm_bytes / hbm_ns if hbm_ns else None,
         "batched_best_point_gbps": max(p["batched_gbps"] for i, p in enumerate(pts)

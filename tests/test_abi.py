@@ -46,7 +46,7 @@ STRUCTS = {
     "sweep_wave_rec_t": ["sum32", "xor32", "hw_id", "xcc_id", "t0", "t1"],
     "sweep_opts_t": ["stream", "cache_policy", "mode", "fixed_iters",
                      "grid_wgs", "pin_occupancy", "wave_out", "lane_out",
-                     "order", "wave_out_cap", "lane_out_cap"],
+                     "order", "wave_out_cap", "lane_out_cap", "fuse"],
     "sweep_result_t": ["target_loads", "issued_loads", "issued_bytes",
                        "mismatch", "sum32", "xor32", "grid_wgs", "wg_threads",
                        "waves", "iters_min", "iters_max", "max_wgs_per_cu",

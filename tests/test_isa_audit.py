@@ -136,7 +136,8 @@ def _kernel_names(text):
     return re.findall(r"^\s+\.name:\s+(\S+)\s*$", text, re.M)
 
 
-@pytest.mark.parametrize("src", ["kernels_plain", "kernels_lds", "kernels_misc", "kernels_chase"])
+@pytest.mark.parametrize("src", ["kernels_plain", "kernels_fused", "kernels_lds", "kernels_misc",
+                                 "kernels_chase"])
 def test_no_kernel_spills_or_uses_scratch(src):
     text = _asm(src)
     names = [n for n in _kernel_names(text) if n.startswith("_Z")]
@@ -168,3 +169,36 @@ def test_reduce_loop_keeps_all_its_loads_in_flight(misc, DT, NL):
     assert waits and waits[0] > loads[-1]
     m = _meta(text, name)
     assert m["vgpr_spill_count"] == 0 and m["private_segment_fixed_size"] == 0
+
+
+@pytest.fixture(scope="module")
+def fused():
+    t = _asm("kernels_fused")
+    return t, _functions(t)
+
+
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+@pytest.mark.parametrize("V", [4, 8, 16])
+@pytest.mark.parametrize("K", range(1, 17))
+def test_fused_batch_keeps_the_K_load_loop(fused, K, V, P):
+    """The fused batch kernel issues its K loads of a group back to back and
+    waits only after the last (the point list is read with scalar loads,
+    which the vector-memory counter does not count), and never has more than
+    K vector loads outstanding."""
+    text, funcs = fused
+    name = f"_ZN3ilp11fused_kloadILi{K}ELi{V}ELi{P}EEEvNS_9FusedArgsE"
+    lines = funcs[name]
+    runs, cur = [], 0
+    for l in lines:
+        if l.startswith("s_waitcnt") and "vmcnt" in l:
+            runs.append(cur)
+            cur = 0
+        elif LOAD.match(l):
+            cur += 1
+    runs.append(cur)
+    assert max(runs) == K and runs.count(K) >= 1, (name, runs)
+    assert sum(bool(LOAD.match(l)) for l in lines) == K, name
+    assert not any(l.startswith(("scratch_", "flat_")) for l in lines), name
+    m = _meta(text, name)
+    assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0
+    assert m["private_segment_fixed_size"] == 0
