@@ -104,6 +104,10 @@ def parse():
                     help="fixed waves per CU for the precision sums instead of "
                          "tuning, e.g. f32=8,bf16=8,fp8_e4m3=4 (for profiling "
                          "the tuned launches alone)")
+    ap.add_argument("--c5a-config", default=None,
+                    help="fixed K,V,waves_per_cu,policy for every batched point "
+                         "instead of tuning, e.g. 3,16,8,1 (for counter runs that "
+                         "must repeat the same launches)")
     ap.add_argument("--json-out", default=None,
                     help="file for the full result (default "
                          "gpurun_out/bench_detail.json); standard output ends "
@@ -661,7 +665,8 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         if not a.no_cpu_baseline:
             vstore = rows.setdefault("c5a_cpu_oracle", {})
             verify = cpu_batch_verifier(vstore, max(1, min(16, os.cpu_count() or 1)))
-        rows["c5a_batched"] = sweeps.batched_autotuned(verify=verify)
+        fixed = tuple(int(v) for v in a.c5a_config.split(",")) if a.c5a_config else None
+        rows["c5a_batched"] = sweeps.batched_autotuned(verify=verify, fixed=fixed)
         rows["c5a_batched"]["wall_s"] = time.perf_counter() - t
     if only in (None, "c5b"):
         t = time.perf_counter()

@@ -410,7 +410,7 @@ def autotune(buf_for_size, sizes, space=None, reps=3, cache_path=None,
 
 def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1),
                       seed=SEED_BASE + 4, cache_path=None, space=None, verify=None,
-                      hi_log2=31):
+                      hi_log2=31, fixed=None):
     """64 sweep points of uneven size (1 MiB .. 2 GiB), laid out back to
     back in one seeded buffer, each read once per pass at its size class's
     tuned (V, K, waves, policy): captured once as a hipGraph, in which the
@@ -420,7 +420,9 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
     at the untuned default.  ``verify``, if given, is called with one (seed, first word,
     words, sum32, xor32) tuple per launch of the first tuned replay and of
     the first untuned pass, and returns one bool per tuple: whether those
-    sinks are the ones the words' oracle gives."""
+    sinks are the ones the words' oracle gives.  ``fixed`` = (K, V, waves
+    per CU, policy) skips the tuning and runs every point with it (for
+    counter runs that must repeat the same launches)."""
     sizes = point_sizes(n_points, hi_log2=hi_log2)
     offs, off = [], 0
     for s in sizes:
@@ -433,7 +435,12 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
         # tune on the largest point's region of a class-sized prefix
         return base
 
-    table = autotune(buf_for, sizes, space=space, cache_path=cache_path)
+    if fixed is None:
+        table = autotune(buf_for, sizes, space=space, cache_path=cache_path)
+    else:
+        K, V, w, pol = fixed
+        table = {c: {"K": K, "vec_width": V, "waves_per_cu": w, "cache_policy": pol}
+                 for c in {size_class(s) for s in sizes}}
 
     def cells_of(cfgs):
         return [isw.make_cell(base + o, s, t["K"], t["vec_width"], t["waves_per_cu"],
@@ -469,7 +476,7 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
         score(name, cfgs)
     # then a local search around the best single configuration: neighbouring
     # K, occupancy, width and policy, two rounds at most
-    for _ in range(2):
+    for _ in range(0 if fixed else 2):
         best = max((n for n in plan_gbps if n != "per_class"), key=plan_gbps.get)
         t0 = plans[best][0]
         K, V, w, pol = key(t0)
