@@ -677,7 +677,7 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         if not a.no_cpu_baseline:
             store = rows.setdefault("c5b_cpu_oracle", {})
             hook = cpu_precision_hook(store, max(1, min(16, os.cpu_count() or 1)))
-        rows["c5b_precision"] = sweeps.precision_sum(waves_fixed=fixed, inspect=hook)
+        rows["c5b_precision"] = sweeps.precision_sum(waves_fixed=fixed, on_payload=hook)
         rows["c5b_precision"]["wall_s"] = time.perf_counter() - t
     if only in (None, "next"):
         t = time.perf_counter()

@@ -589,12 +589,12 @@ def batched_autotuned(n_points=64, n=10, default=(16, 2, 16, isw.CACHE_BYPASS_L1
 
 # ----------------------------------------------- precision reduction (C5b)
 def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 32),
-                  seed=SEED_BASE + 5, waves_fixed=None, inspect=None):
+                  seed=SEED_BASE + 5, waves_fixed=None, on_payload=None):
     """Streaming FP32 / BF16 / FP8 sums of N(0,1) payloads.  The occupancy
     is tuned per payload type (median of 3 launches per choice), then n
     launches are timed at the chosen occupancy.  ``waves_fixed`` ({kind:
-    waves_per_cu}) skips the tuning for the kinds it names.  ``inspect``,
-    if given, is called as inspect(kind, payload, n_elements, row) after a
+    waves_per_cu}) skips the tuning for the kinds it names.  ``on_payload``,
+    if given, is called as on_payload(kind, payload, n_elements, row) after a
     kind's launches, while its payload is still on the device; what it
     returns (a dict) is merged into the kind's row."""
     import synth
@@ -626,8 +626,8 @@ def precision_sum(payload_bytes=4 * GIB, n=10, waves_choices=(4, 8, 12, 16, 24, 
                      "median_gbps": _median(gs),
                      "frac_of_hbm_peak": _median(gs) / stats.HBM_PEAK_GBPS,
                      "waves": r["waves"], "grid_wgs": r["grid_wgs"]}
-        if inspect is not None:
-            out[kind].update(inspect(kind, p, n_el, out[kind]))
+        if on_payload is not None:
+            out[kind].update(on_payload(kind, p, n_el, out[kind]))
         del p
     return out
 
