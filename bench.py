@@ -683,7 +683,7 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         t = time.perf_counter()
         MIB = 1 << 20
         rows["f2_f3_order_footprint"] = sweeps.order_footprint(
-            [2 * MIB, 16 * MIB, 128 * MIB, GIB, 4 * GIB])
+            [2 * MIB, 4 * MIB, 8 * MIB, 16 * MIB, 128 * MIB, GIB, 4 * GIB])
         rows["f2_f3_order_footprint"]["wall_s"] = time.perf_counter() - t
         t = time.perf_counter()
         rows["f4_regime_map"] = sweeps.regime_map()

@@ -81,6 +81,12 @@ extern "C" {
 #define SWEEP_ORDER_ROUND_ROBIN 0  /* wave w: q = w, w + n_waves, ...        */
 #define SWEEP_ORDER_BLOCKED     1  /* wave w: q = w*G .. w*G+G-1,
                                       G = ceil(Q / n_waves)                    */
+#define SWEEP_ORDER_STRIDED     2  /* dealt round robin, but load j of group q
+                                      reads segment j*Q + q: a group's K loads
+                                      go to K regions Q segments apart instead
+                                      of K adjacent segments (the vectors read
+                                      over a cell, and so its global sinks,
+                                      are those of the other orders)           */
 
 /* ----------------------------------------------------------------- kinds */
 #define SWEEP_KIND_PLAIN        0  /* K independent loads into registers      */

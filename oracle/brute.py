@@ -8,11 +8,14 @@ buffer, so the two pin each other on small cases.
 """
 
 
-def simulate(words, V, K, Q, n_waves, base=0, n_vec=None, blocked=False):
+def simulate(words, V, K, Q, n_waves, base=0, n_vec=None, blocked=False,
+             strided=False):
     """Return per-lane sinks as a dict {(wave, lane): (sum32, xor32)}.
 
     Round robin: wave w takes groups w, w + n_waves, ...; blocked: wave w
-    takes the w-th run of ceil(Q / n_waves) consecutive groups.
+    takes the w-th run of ceil(Q / n_waves) consecutive groups.  Load j of
+    group q reads the segment after the group's previous load (q*K + j), or
+    with ``strided`` the segment j*Q + q.
     """
     wpv = V // 4
     if n_vec is None:
@@ -29,8 +32,9 @@ def simulate(words, V, K, Q, n_waves, base=0, n_vec=None, blocked=False):
             q, step, stop = w, n_waves, Q
         while q < stop:                    # this wave's iterations
             for j in range(K):             # K independent loads
+                seg = j * Q + q if strided else q * K + j
                 for lane in range(64):
-                    v = base + ((q * K + j) * 64 + lane) % n_vec
+                    v = base + (seg * 64 + lane) % n_vec
                     acc = lanes[(w, lane)]
                     for t in range(wpv):
                         word = int(words[v * wpv + t])

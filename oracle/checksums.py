@@ -16,7 +16,9 @@ and fully coalesced at every K; only the per-thread offered count changes):
                   ``plan.groups_of_wave``
     load j of K   lane l reads vector  v = ((q*K + j)*64 + l) mod n_vec
                   of a region of n_vec vectors of V bytes, starting at
-                  vector ``base`` of the buffer.
+                  vector ``base`` of the buffer; in the strided layout
+                  (the address-ordering experiment Section 4.2 proposes)
+                  v = ((j*Q + q)*64 + l) mod n_vec instead.
 
 A vector of V bytes is V/4 consecutive little-endian 32-bit words.
 
@@ -31,13 +33,22 @@ WAVE = 64
 MASK32 = np.uint64(0xFFFFFFFF)
 
 
-def vector_index(q, j, lane, K, n_vec):
-    """Vector read by ``lane`` for load ``j`` of wave-group ``q``."""
+def vector_index(q, j, lane, K, n_vec, Q=None, order=plan.ROUND_ROBIN):
+    """Vector read by ``lane`` for load ``j`` of wave-group ``q``: the K
+    loads of a group are adjacent 64-lane segments, (q*K + j)*64 + lane;
+    in the strided layout they are Q segments apart, (j*Q + q)*64 + lane."""
+    if order == plan.STRIDED:
+        return ((j * Q + q) * WAVE + lane) % n_vec
     return ((q * K + j) * WAVE + lane) % n_vec
 
 
-def _group_vectors(q0, q1, K, n_vec):
+def _group_vectors(q0, q1, K, n_vec, Q=None, order=plan.ROUND_ROBIN):
     """Vector indices of groups q0..q1-1 as an array [groups, K, 64]."""
+    if order == plan.STRIDED:
+        q = np.arange(q0, q1, dtype=np.int64)[:, None, None]
+        j = np.arange(K, dtype=np.int64)[None, :, None]
+        lane = np.arange(WAVE, dtype=np.int64)[None, None, :]
+        return ((j * Q + q) * WAVE + lane) % n_vec
     f = np.arange(q0 * K * WAVE, q1 * K * WAVE, dtype=np.int64)
     return (f % n_vec).reshape(q1 - q0, K, WAVE)
 
@@ -61,7 +72,7 @@ def per_lane(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
     x = np.zeros((n_waves, WAVE), dtype=np.uint32)
     for q0 in range(0, Q, chunk_groups):
         q1 = min(Q, q0 + chunk_groups)
-        v = _group_vectors(q0, q1, K, n_vec)              # [g, K, 64]
+        v = _group_vectors(q0, q1, K, n_vec, Q, order)    # [g, K, 64]
         w = vec[v]                                          # [g, K, 64, V/4]
         gs = w.astype(np.uint64).sum(axis=(1, 3))           # [g, 64]
         gx = np.bitwise_xor.reduce(w, axis=3)
@@ -74,7 +85,7 @@ def per_lane(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
 
 def _owners(q0, q1, Q, n_waves, order):
     q = np.arange(q0, q1)
-    if order == plan.ROUND_ROBIN:
+    if order in (plan.ROUND_ROBIN, plan.STRIDED):
         return q % n_waves
     return q // -(-Q // n_waves)
 
@@ -89,7 +100,7 @@ def per_wave(words_u32, V, K, Q, n_waves, base=0, n_vec=None,
     x = np.zeros(n_waves, dtype=np.uint32)
     for q0 in range(0, Q, chunk_groups):
         q1 = min(Q, q0 + chunk_groups)
-        v = _group_vectors(q0, q1, K, n_vec)
+        v = _group_vectors(q0, q1, K, n_vec, Q, order)
         w = vec[v].reshape(q1 - q0, -1)                     # [g, K*64*V/4]
         gs = w.astype(np.uint64).sum(axis=1)
         gx = np.bitwise_xor.reduce(w, axis=1)
@@ -128,10 +139,9 @@ def wave_from_seed(seed, V, K, Q, n_waves, wave, base=0, n_vec=None,
     s = 0
     x = 0
     for q in plan.groups_of_wave(wave, Q, n_waves, order):
-        f0 = q * K * WAVE
-        # the group's K*64 vectors are consecutive modulo n_vec
-        f = np.arange(f0, f0 + K * WAVE, dtype=np.int64) % n_vec + base
-        # one contiguous or two (wrapped) runs; generate run by run
+        f = _group_vectors(q, q + 1, K, n_vec, Q, order).ravel() + base
+        # runs of consecutive vectors (one per segment at most, or the whole
+        # group when its loads are adjacent); generate run by run
         starts = np.flatnonzero(np.diff(f) != 1) + 1
         for run in np.split(f, starts):
             w = splitmix.words(seed, int(run[0]) * wpv, run.size * wpv)
@@ -148,7 +158,7 @@ def lane_from_seed(seed, V, K, Q, n_waves, wave, lane, n_vec,
     x = 0
     for q in plan.groups_of_wave(wave, Q, n_waves, order):
         for j in range(K):
-            v = vector_index(q, j, lane, K, n_vec)
+            v = vector_index(q, j, lane, K, n_vec, Q, order)
             w = splitmix.words(seed, v * wpv, wpv)
             s += int(w.astype(np.uint64).sum())
             x ^= int(np.bitwise_xor.reduce(w))

@@ -6,8 +6,9 @@ over 20,000 MiB, at most 84 %) because it collects no address trace, and
 the discriminating experiment proposed after Table 2 asks for
 address-trace coverage.  The address map makes the trace exact: load j of
 wave-group q covers the 64-lane segment (64 consecutive vectors) number
-(q*K + j) mod n_seg of the allocation, where n_seg = n_vec / 64, and every
-group below Q is handled by exactly one wave (``plan.groups_of_wave``).
+(q*K + j) mod n_seg of the allocation (or (j*Q + q) mod n_seg in the
+strided layout), where n_seg = n_vec / 64, and every group below Q is
+handled by exactly one wave (``plan.groups_of_wave``).
 
 ``segment_reads`` walks every wave's groups in the order that wave handles
 them and counts the reads of every segment; ``line_coverage`` turns the
@@ -31,6 +32,15 @@ def segment_reads(alloc_bytes, V, K, Q, n_waves, order=plan.ROUND_ROBIN):
     n_seg = alloc_bytes // V // WAVE
     if n_seg * WAVE * V != alloc_bytes:
         raise ValueError("allocation must be whole 64-lane segments")
+    if order == plan.STRIDED:
+        # load j of group q reads segment (j*Q + q) mod n_seg
+        counts = np.zeros(n_seg, dtype=np.int64)
+        for w in range(n_waves):
+            g = plan.groups_of_wave(w, Q, n_waves, order)
+            q = np.arange(g.start, g.stop, g.step, dtype=np.int64)
+            for j in range(K):
+                np.add.at(counts, (j * Q + q) % n_seg, 1)
+        return counts
     diff = np.zeros(n_seg + 1, dtype=np.int64)
     for w in range(n_waves):
         g = plan.groups_of_wave(w, Q, n_waves, order)
@@ -81,8 +91,9 @@ def lane_line_reads(alloc_bytes, V, K, Q, n_waves, order=plan.ROUND_ROBIN):
         for q in plan.groups_of_wave(w, Q, n_waves, order):
             for j in range(K):
                 lines = set()
+                seg = j * Q + q if order == plan.STRIDED else q * K + j
                 for lane in range(WAVE):
-                    v = ((q * K + j) * WAVE + lane) % n_vec
+                    v = (seg * WAVE + lane) % n_vec
                     lines.add(v * V // LINE)
                 for ln in lines:
                     counts[ln] += 1

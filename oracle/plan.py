@@ -37,7 +37,7 @@ def per_thread_floor(L, threads, K):
             "issued": iters * K * threads}
 
 
-ROUND_ROBIN, BLOCKED = 0, 1
+ROUND_ROBIN, BLOCKED, STRIDED = 0, 1, 2
 
 
 def groups_of_wave(w, Q, n_waves, order=ROUND_ROBIN):
@@ -46,10 +46,12 @@ def groups_of_wave(w, Q, n_waves, order=ROUND_ROBIN):
     round robin: q = w, w + n_waves, ... (neighbouring waves read
                  neighbouring groups at the same time);
     blocked:     q = w*G .. w*G + G - 1 with G = ceil(Q / n_waves) (every
-                 wave streams its own contiguous range).
+                 wave streams its own contiguous range);
+    strided:     dealt as round robin (only the loads' addresses differ,
+                 see ``checksums.vector_index``).
     Either way every group below Q is handled exactly once.
     """
-    if order == ROUND_ROBIN:
+    if order in (ROUND_ROBIN, STRIDED):
         return range(w, Q, n_waves)
     G = -(-Q // n_waves)
     return range(min(Q, w * G), min(Q, (w + 1) * G))
@@ -57,7 +59,7 @@ def groups_of_wave(w, Q, n_waves, order=ROUND_ROBIN):
 
 def owner(q, Q, n_waves, order=ROUND_ROBIN):
     """The wave that handles group ``q``."""
-    if order == ROUND_ROBIN:
+    if order in (ROUND_ROBIN, STRIDED):
         return q % n_waves
     return q // -(-Q // n_waves)
 

@@ -13,11 +13,14 @@ namespace ilp {
 constexpr int kMaxK = 16;
 constexpr int kPlainWgThreads = 256;   // 4 waves, one per SIMD
 
-// Plain K-load cell.  Round robin: wave w of n_waves handles wave-groups
-// q = w, w + n_waves, ... below Q; blocked: q = w*G .. w*G + G - 1.  Load j
-// of group q reads the 64 vectors starting at vector (q*K + j)*64 mod n_vec.
-// `stride` is the vector step between a wave's consecutive groups, mod
-// n_vec: n_waves*K*64 (round robin) or K*64 (blocked).
+// Plain K-load cell.  Round robin (and strided): wave w of n_waves handles
+// wave-groups q = w, w + n_waves, ... below Q; blocked: q = w*G .. w*G +
+// G - 1.  Load j of group q reads the 64 vectors starting at vector
+// (q*gstep + j*jstep) mod n_vec: gstep = K*64, jstep = 64 (adjacent
+// segments, (q*K + j)*64), or in the strided layout gstep = 64, jstep =
+// Q*64 ((j*Q + q)*64).  `stride` is the vector step between a wave's
+// consecutive groups, mod n_vec: n_waves*gstep (round robin, strided) or
+// gstep (blocked).
 struct PlainArgs {
   const uint8_t* buf;
   uint64_t n_vec;
@@ -27,6 +30,8 @@ struct PlainArgs {
   uint32_t* lane_out;
   uint64_t G;          // groups per wave in blocked order
   uint32_t order;      // SWEEP_ORDER_*
+  uint64_t gstep;      // start vector of group q: q * gstep (mod n_vec)
+  uint64_t jstep;      // from load j to load j + 1 (mod n_vec), below n_vec
 };
 
 // Fused batch of plain cells that share K, vector width, cache policy and

@@ -2,7 +2,8 @@
 // axis K" and Section 4.2).
 //
 // One wavefront-iteration issues K independent loads - each one contiguous,
-// coalesced 64-lane segment of 64*V bytes - into K distinct register sets,
+// coalesced 64-lane segment of 64*V bytes, adjacent to each other or (the
+// strided layout) Q segments apart - into K distinct register sets,
 // and only then folds them, oldest first; nothing from the next iteration is
 // in flight meanwhile, so a wave has at most K loads outstanding.  The loop
 // itself never stores: the sinks leave the kernel in one record per wave.
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(kPlainWgThreads) void plain_kload(PlainArgs a) {
   }
   // start vector of the first group, advanced by `stride` per iteration,
   // both modulo the buffer's vector count
-  uint64_t p = (q0 * (K * kWave)) % a.n_vec;
+  uint64_t p = (q0 * a.gstep) % a.n_vec;
 #pragma unroll 1
   for (uint64_t q = q0; q < q1; q += qs) {
     typename Vec<V>::T v[K];
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(kPlainWgThreads) void plain_kload(PlainArgs a) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       v[j] = load_seg<V, POL>(a.buf + pj * V, lane);
-      pj += kWave;
+      pj += a.jstep;
       if (pj >= a.n_vec) pj -= a.n_vec;
     }
     // all K loads are issued before the first is consumed: without this

@@ -53,7 +53,8 @@ int plan_cell(const PlanIn& in, Plan* out, std::string* err) {
   if (in.mode != SWEEP_FIXED_WORK && in.mode != SWEEP_FIXED_ITERS &&
       in.mode != SWEEP_PER_THREAD_FLOOR)
     return bad(err, SWEEP_EINVAL, "unknown work mode");
-  if (in.order != SWEEP_ORDER_ROUND_ROBIN && in.order != SWEEP_ORDER_BLOCKED)
+  if (in.order != SWEEP_ORDER_ROUND_ROBIN && in.order != SWEEP_ORDER_BLOCKED &&
+      in.order != SWEEP_ORDER_STRIDED)
     return bad(err, SWEEP_EINVAL, "unknown work-group order");
   if (!plain && in.order != SWEEP_ORDER_ROUND_ROBIN)
     return bad(err, SWEEP_EINVAL, "the LDS paths deal work-groups round robin only");
@@ -103,8 +104,14 @@ int plan_cell(const PlanIn& in, Plan* out, std::string* err) {
   o.mismatch = in.mode == SWEEP_FIXED_ITERS
                    ? 0.0
                    : (double)(in.L - o.issued_loads) / (double)in.L;
-  p.stride = in.order == SWEEP_ORDER_BLOCKED ? (K * 64ull) % o.n_vec
-                                             : (nw * K * 64ull) % o.n_vec;
+  // contiguous layouts: group q starts at vector q*K*64 and its loads are
+  // adjacent segments; strided: group q starts at q*64 and load j is
+  // j*Q segments further on
+  const bool strided = in.order == SWEEP_ORDER_STRIDED;
+  p.gstep = strided ? 64ull : K * 64ull;
+  p.jstep = strided ? (o.Q * 64ull) % o.n_vec : 64ull % o.n_vec;
+  p.stride = in.order == SWEEP_ORDER_BLOCKED ? p.gstep % o.n_vec
+                                             : (nw * p.gstep) % o.n_vec;
   o.lds_pad_bytes = pin_padding(p.wgs_per_cu, p.lds_ring_bytes, in.lds_per_cu,
                                 in.lds_per_wg_max);
   *out = p;

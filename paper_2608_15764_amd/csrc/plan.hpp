@@ -31,6 +31,8 @@ struct PlanIn {
 struct Plan {
   sweep_plan_t pub{};
   uint64_t stride = 0;       // vector step between a wave's groups, mod n_vec
+  uint64_t gstep = 0;        // vector step from group q to q + 1 (start vectors)
+  uint64_t jstep = 0;        // vector step from load j to j + 1 of a group, mod n_vec
   uint64_t G = 0;            // groups per wave in blocked order
   uint32_t wg_waves = 0;     // waves per workgroup
   uint32_t wgs_per_cu = 0;   // residency the grid asks for

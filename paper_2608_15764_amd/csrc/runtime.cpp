@@ -291,7 +291,8 @@ hipError_t enqueue(const Prepared& p, hipStream_t st, sweep_wave_rec_t* rec,
                    uint32_t* lane_out, hipEvent_t e0, hipEvent_t e1) {
   if (p.c.kind == SWEEP_KIND_PLAIN) {
     const PlainArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,
-                      p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order};
+                      p.plan.stride, rec, lane_out, p.plan.G, (uint32_t)p.c.order,
+                      p.plan.gstep, p.plan.jstep};
     return launch_timed(p.fn, p.grid, p.threads, p.lds, st, a, e0, e1);
   }
   const LdsArgs a{static_cast<const uint8_t*>(p.c.buf), p.plan.pub.n_vec, p.plan.pub.Q,

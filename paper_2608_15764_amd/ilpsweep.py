@@ -20,7 +20,7 @@ FIXED_WORK, FIXED_ITERS, PER_THREAD_FLOOR = 0, 1, 2
 CACHE_DEFAULT, CACHE_NT, CACHE_BYPASS_L1, CACHE_BYPASS_L1_NT = 0, 1, 2, 3
 POLICY_NAMES = {"default": 0, "nt": 1, "bypass_l1": 2, "bypass_l1_nt": 3}
 KIND_PLAIN, KIND_LDS_ASYNC, KIND_LDS_MATCHED = 0, 1, 2
-ORDER_ROUND_ROBIN, ORDER_BLOCKED = 0, 1
+ORDER_ROUND_ROBIN, ORDER_BLOCKED, ORDER_STRIDED = 0, 1, 2
 F32, BF16, FP8_E4M3 = 0, 1, 2
 
 

@@ -663,17 +663,21 @@ def allocation_counter_pass(sizes, Ks=(2, 8), waves_per_cu=16, L=1 << 30,
 # --------------------------- order and footprint experiment (next rows f2, f3)
 def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
                     policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 6):
-    """The fixed-work K sweep under both work-group orders, at allocations
+    """The fixed-work K sweep under three address orderings, at allocations
     below, around and above the caches (4 MiB L2 per XCD, 256 MiB last-level
     cache).  Coalescing, occupancy and logical bytes are the same in every
-    cell; only the address ordering (round robin vs blocked) and the
-    footprint change."""
+    cell; only the address ordering and the footprint change: round robin
+    (a group's K loads are adjacent segments, neighbouring waves read
+    neighbouring groups), blocked (every wave streams its own range) and
+    strided (round robin, but a group's K loads go to K regions Q segments
+    apart, so the K-dependent part of the aggregate order changes)."""
     buf = device_buffer(max(sizes), seed)
     out = {}
     for size in sizes:
         row = {}
         for order, oname in ((isw.ORDER_ROUND_ROBIN, "round_robin"),
-                             (isw.ORDER_BLOCKED, "blocked")):
+                             (isw.ORDER_BLOCKED, "blocked"),
+                             (isw.ORDER_STRIDED, "strided")):
             cells, meta = [], []
             for direction in ("asc", "rev"):
                 ks = list(Ks) if direction == "asc" else list(reversed(list(Ks)))
@@ -692,7 +696,8 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
             row[oname] = {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
                           "coverage": {K: _coverage_row(size, 16, n)
                                        for K, n in sorted(issued.items())},
-                          "front_duplicates": {
+                          # lock-step model of the adjacent layouts only
+                          "front_duplicates": None if order == isw.ORDER_STRIDED else {
                               K: round(stats.front_duplicates(
                                   order == isw.ORDER_BLOCKED, K, n_waves, L // (64 * K),
                                   size // 16), 4) for K in Ks},

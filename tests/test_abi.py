@@ -129,6 +129,17 @@ def test_planner_blocked_order(isw, K, w, L):
     assert (p["iters_min"], p["iters_max"]) == (o["iters_min"], o["iters_max"])
 
 
+@pytest.mark.parametrize("K,w,L", [(1, 4, 2**26), (3, 12, 2**26 + 999), (16, 32, 10**6)])
+def test_planner_strided_layout(isw, K, w, L):
+    """The strided layout deals its groups round robin: the same plan."""
+    p = isw.sweep_plan(2**30, K, 16, w, L, num_cus=256, order=isw.ORDER_STRIDED)
+    o = oplan.wave_group(L, K, 256 * w, order=oplan.STRIDED)
+    assert p["Q"] == o["Q"] and p["issued_loads"] == o["issued"]
+    assert (p["iters_min"], p["iters_max"]) == (o["iters_min"], o["iters_max"])
+    with pytest.raises(isw.SweepError):
+        isw.sweep_plan(2**30, K, 16, w, L, num_cus=256, order=3)
+
+
 def test_planner_explicit_grid(isw):
     p = isw.sweep_plan(64 << 20, 2, 4, 4, 2**24, num_cus=0, grid_wgs=256)
     assert p["grid_wgs"] == 256 and p["waves"] == 1024
@@ -157,5 +168,5 @@ def test_planner_rejects_unknown_mode(isw):
         isw.sweep_plan(1 << 20, 2, 16, 8, 1000, mode=7, num_cus=256)
     assert e.value.code == -1
     with pytest.raises(isw.SweepError) as e:
-        isw.sweep_plan(1 << 20, 2, 16, 8, 1000, num_cus=256, order=2)
+        isw.sweep_plan(1 << 20, 2, 16, 8, 1000, num_cus=256, order=3)
     assert e.value.code == -1

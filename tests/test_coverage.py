@@ -16,7 +16,7 @@ TINY = [  # (alloc bytes, V, K, Q, n_waves)
 ]
 
 
-@pytest.mark.parametrize("order", [plan.ROUND_ROBIN, plan.BLOCKED])
+@pytest.mark.parametrize("order", [plan.ROUND_ROBIN, plan.BLOCKED, plan.STRIDED])
 @pytest.mark.parametrize("alloc,V,K,Q,n_waves", TINY)
 def test_walk_matches_lane_brute_force(alloc, V, K, Q, n_waves, order):
     brute = coverage.lane_line_reads(alloc, V, K, Q, n_waves, order)
@@ -46,7 +46,7 @@ def test_paper_bound_for_the_largest_allocation():
     assert small["coverage"] == 1.0 and small["max_reads"] == 33
 
 
-@pytest.mark.parametrize("order", [plan.ROUND_ROBIN, plan.BLOCKED])
+@pytest.mark.parametrize("order", [plan.ROUND_ROBIN, plan.BLOCKED, plan.STRIDED])
 @pytest.mark.parametrize("alloc,V,K,L,n_waves", [
     (1 << 20, 16, 3, 1 << 17, 96), (1 << 20, 4, 5, 1 << 20, 64),
     (2 << 20, 8, 16, 1 << 16, 256), (3 << 20, 16, 7, 1 << 20, 1024),

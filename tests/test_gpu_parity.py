@@ -446,6 +446,28 @@ def test_plain_blocked_order_matches_oracle(V, K, w, grid, n_vec, L):
     assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
 
 
+@pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES)
+def test_plain_strided_layout_matches_oracle(V, K, w, grid, n_vec, L):
+    """Strided layout: load j of group q reads segment j*Q + q."""
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=V * 11 + K, device="cuda")
+    n_waves = grid * 4
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=isw.CACHE_BYPASS_L1_NT,
+                         lane_out=lo, wave_out=ro, order=isw.ORDER_STRIDED)
+    r = isw.sweep_plain(buf, nbytes, K, V, w, L, opts)
+    p = oplan.wave_group(L, K, n_waves, order=oplan.STRIDED)
+    assert r["issued_loads"] == p["issued"]
+    ws, wx = checksums.per_lane(host_words(buf), V, K, p["Q"], n_waves,
+                                order=oplan.STRIDED)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    # the global sinks are the adjacent layout's
+    rr = isw.sweep_plain(buf, nbytes, K, V, w, L, isw.make_opts(grid_wgs=grid))
+    assert (r["sum32"], r["xor32"]) == (rr["sum32"], rr["xor32"])
+
+
 def test_lds_paths_reject_blocked_order():
     buf = dev_bytes(1 << 20)
     with pytest.raises(isw.SweepError) as e:
@@ -543,7 +565,7 @@ def test_sweep_drivers_run_small():
     al = sweeps.allocation_sweep([1 << 20, 4 << 20], Ks=(1, 2), waves_list=(8,), L=1 << 20, n=1)
     assert all(v["checksums_consistent"] for v in al.values())
     of = sweeps.order_footprint([1 << 20, 2 << 20], Ks=(1, 2), L=1 << 18, n=1)
-    assert set(of[1 << 20]) == {"round_robin", "blocked"}
+    assert set(of[1 << 20]) == {"round_robin", "blocked", "strided"}
     man = sweeps.lds_counter_pass(nbytes=4 << 20, waves_list=(1,), depths=(2, 5), L=1 << 18,
                                   reps=2)
     assert len(man) == 8 and {m["path"] for m in man} == {"lds_async", "lds_matched"}
@@ -603,6 +625,8 @@ def test_new_bench_rows_run_small():
         assert sum(b["counts"].values()) == 4 and b["launches_per_cell"] == 2
     of = sweeps.order_footprint([1 << 20, 4 << 20], Ks=(1, 2), L=1 << 17, n=1)
     assert of[4 << 20]["blocked"]["coverage"][2]["coverage"] == 0.5
+    assert of[4 << 20]["strided"]["coverage"][2]["coverage"] == 0.5
+    assert of[1 << 20]["strided"]["checksums_consistent"]
     assert of[1 << 20]["round_robin"]["coverage"][1]["max_reads"] == 2
     seen = []
 

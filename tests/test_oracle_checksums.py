@@ -150,9 +150,41 @@ def test_blocked_order_matches_brute_force(V, K, Q, nw, nbytes):
                                         order=plan.BLOCKED) == (ws[wave], wx[wave])
 
 
+@pytest.mark.parametrize("V,K,Q,nw,nbytes", CASES)
+def test_strided_layout_matches_brute_force(V, K, Q, nw, nbytes):
+    """The strided layout (load j of group q reads segment j*Q + q): the
+    vectorised oracle equals the lane-by-lane simulation, per lane, per
+    wave and from the seed; the cell's global sinks equal the adjacent
+    layout's, since both read the stream 0 .. 64 K Q - 1 modulo the
+    region."""
+    w = _buf(nbytes, seed=23)
+    lanes = brute.simulate(w, V, K, Q, nw, strided=True)
+    s, x = checksums.per_lane(w, V, K, Q, nw, order=plan.STRIDED)
+    for (wave, lane), (ls, lx) in lanes.items():
+        assert (s[wave, lane], x[wave, lane]) == (ls, lx)
+    ws, wx = checksums.per_wave(w, V, K, Q, nw, order=plan.STRIDED, chunk_groups=3)
+    for wave in range(nw):
+        assert checksums.wave_from_seed(23, V, K, Q, nw, wave, buffer_bytes=nbytes,
+                                        order=plan.STRIDED) == (ws[wave], wx[wave])
+        lane = (7 * wave) % 64
+        assert checksums.lane_from_seed(23, V, K, Q, nw, wave, lane, nbytes // V,
+                                        order=plan.STRIDED) == (s[wave, lane], x[wave, lane])
+    rs, rx = checksums.per_wave(w, V, K, Q, nw)
+    assert checksums.combine(ws, wx) == checksums.combine(rs, rx)
+
+
+def test_strided_vector_index_spreads_a_groups_loads():
+    # Q = 5 groups of K = 3 loads over 15 segments: group 2 reads 2, 7, 12
+    n_vec = 15 * 64
+    got = [checksums.vector_index(2, j, 0, 3, n_vec, Q=5, order=plan.STRIDED) // 64
+           for j in range(3)]
+    assert got == [2, 7, 12]
+    assert [checksums.vector_index(2, j, 0, 3, n_vec) // 64 for j in range(3)] == [6, 7, 8]
+
+
 def test_orders_partition_the_same_groups():
     for Q, nw in [(0, 3), (1, 4), (7, 3), (12, 4), (13, 4), (100, 7)]:
-        for order in (plan.ROUND_ROBIN, plan.BLOCKED):
+        for order in (plan.ROUND_ROBIN, plan.BLOCKED, plan.STRIDED):
             seen = sorted(q for w in range(nw) for q in plan.groups_of_wave(w, Q, nw, order))
             assert seen == list(range(Q))
             for w in range(nw):
