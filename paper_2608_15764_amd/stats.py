@@ -119,38 +119,47 @@ def anomalous_launches(samples, frac=0.9):
     return out
 
 
-def front_duplicates(blocked, K, n_waves, Q, n_vec, max_iters=64):
-    """Share of the loads of one lock-step iteration that read a segment
-    another wave reads in the same iteration.
+def front_duplicates(order, K, n_waves, Q, n_vec, max_iters=64):
+    """Share of the loads of one lock-step iteration that read a 64-vector
+    segment another load of the same iteration reads.
 
     Model of the f3 ordering experiment: every wave runs its i-th iteration
-    at the same time.  In round-robin order wave w takes group
-    q = i * n_waves + w, in blocked order q = w * G + i (G = ceil(Q /
-    n_waves)); a group starts at vector (q * K * 64) mod n_vec.  When the
-    volume wraps the allocation, groups of different waves can start at the
-    same vector, and those loads meet the data in a cache.  Averaged over up
-    to ``max_iters`` iterations spread evenly over the run.  Assumes n_vec is
-    a multiple of 64 * K (aligned groups), as in every cell measured."""
+    at the same time, and the front is the K loads of every wave.  The
+    owners: round robin (order 0) and strided (order 2) give wave w group
+    q = i * n_waves + w, blocked (order 1) q = w * G + i (G = ceil(Q /
+    n_waves)).  The segments: in the adjacent layouts (orders 0 and 1) load
+    j of group q reads segment (q * K + j) mod S, in the strided one
+    (j * Q + q) mod S, with S = n_vec / 64 segments in the allocation.
+    When the volume wraps the allocation, loads of different waves, and in
+    the strided layout the K loads of one wave, can read the same segment,
+    and the repeats meet the data in a cache.  Averaged over up to
+    ``max_iters`` iterations spread evenly over the run.  Assumes n_vec is a
+    multiple of 64, so that every load reads one whole segment."""
     import numpy as np
-    if Q <= 0 or n_waves <= 0:
+    order = int(order)
+    if order not in (0, 1, 2):
+        raise ValueError(f"unknown order {order}")
+    if Q <= 0 or n_waves <= 0 or K <= 0:
         return 0.0
+    if n_vec % 64:
+        raise ValueError("n_vec must be a multiple of 64")
+    S = n_vec // 64
     G = -(-Q // n_waves)
-    n_it = G
-    its = np.unique(np.linspace(0, n_it - 1, min(n_it, max_iters)).astype(np.int64))
+    its = np.unique(np.linspace(0, G - 1, min(G, max_iters)).astype(np.int64))
     w = np.arange(n_waves, dtype=np.int64)
+    j = np.arange(K, dtype=np.int64)
     total = dup = 0
     for i in its:
-        if blocked:
-            q = w * G + i
-            q = q[(q < Q) & (i < G)]
-        else:
-            q = i * n_waves + w
-            q = q[q < Q]
+        q = w * G + i if order == 1 else i * n_waves + w
+        q = q[q < Q]
         if q.size == 0:
             continue
-        starts = (q * K * 64) % n_vec
-        total += q.size
-        dup += q.size - np.unique(starts).size
+        if order == 2:
+            seg = (j[None, :] * Q + q[:, None]) % S
+        else:
+            seg = (q[:, None] * K + j[None, :]) % S
+        total += seg.size
+        dup += seg.size - np.unique(seg).size
     return dup / total if total else 0.0
 
 

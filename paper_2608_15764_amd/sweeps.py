@@ -696,11 +696,10 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
             row[oname] = {"median_gbps": {k: round(v, 1) for k, v in c["median_gbps"].items()},
                           "coverage": {K: _coverage_row(size, 16, n)
                                        for K, n in sorted(issued.items())},
-                          # lock-step model of the adjacent layouts only
-                          "front_duplicates": None if order == isw.ORDER_STRIDED else {
+                          "front_duplicates": {
                               K: round(stats.front_duplicates(
-                                  order == isw.ORDER_BLOCKED, K, n_waves, L // (64 * K),
-                                  size // 16), 4) for K in Ks},
+                                  order, K, n_waves, L // (64 * K), size // 16), 4)
+                              for K in Ks},
                           "decline_2_8": c.get("decline_2_8"),
                           "by_order": c["by_order"],
                           "residency_flags": summ["residency_flags"],

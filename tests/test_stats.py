@@ -111,29 +111,45 @@ def test_anomalous_launches_are_disclosed():
 def test_front_duplicates_closed_forms():
     # round robin: the front of one iteration is contiguous, n_waves groups;
     # no sharing while it fits the allocation
-    assert stats.front_duplicates(False, 2, 8, 64, 64 * 2 * 16) == 0.0
+    assert stats.front_duplicates(0, 2, 8, 64, 64 * 2 * 16) == 0.0
     # blocked over 4 passes: wave w reads groups 4w..4w+3 of a 4-group
     # allocation, so in every iteration all four waves read the same group
-    assert stats.front_duplicates(True, 1, 4, 16, 64 * 4) == 0.75
+    assert stats.front_duplicates(1, 1, 4, 16, 64 * 4) == 0.75
     # round robin with a front of 8 groups over a 4-group allocation: each
     # segment is read twice per iteration
-    assert stats.front_duplicates(False, 1, 8, 64, 64 * 4) == 0.5
+    assert stats.front_duplicates(0, 1, 8, 64, 64 * 4) == 0.5
+    # strided, Q a multiple of the allocation's 16 segments: the K loads of
+    # a group all read segment q mod 16, so K - 1 of every K repeat
+    for K in (1, 2, 4, 8):
+        assert stats.front_duplicates(2, K, 4, 64, 64 * 16) == (K - 1) / K
+    # strided without a wrap (K Q segments in the allocation): all distinct
+    assert stats.front_duplicates(2, 4, 8, 64, 64 * 4 * 64) == 0.0
+    # strided, Q = S / 2: loads j and j + 2 of a group meet
+    assert stats.front_duplicates(2, 4, 2, 8, 64 * 16) == 0.5
+    with pytest.raises(ValueError):
+        stats.front_duplicates(3, 1, 1, 1, 64)
 
 
-def test_front_duplicates_matches_brute_force():
-    from oracle import plan as oplan
-    for blocked, K, nw, Q, nv in [(False, 3, 5, 47, 64 * 3 * 4), (True, 3, 5, 47, 64 * 3 * 4),
-                                  (True, 2, 6, 100, 64 * 2 * 10), (False, 1, 16, 40, 64 * 7)]:
-        order = oplan.BLOCKED if blocked else oplan.ROUND_ROBIN
-        lists = [list(oplan.groups_of_wave(w, Q, nw, order)) for w in range(nw)]
-        n_it = max(len(x) for x in lists)
-        total = dup = 0
-        for i in range(n_it):
-            qs = [x[i] for x in lists if i < len(x)]
-            starts = [(q * K * 64) % nv for q in qs]
-            total += len(qs)
-            dup += len(qs) - len(set(starts))
-        assert stats.front_duplicates(blocked, K, nw, Q, nv, max_iters=10**6) == dup / total
+def _front_brute(order, K, nw, Q, nv):
+    from oracle import checksums, plan as oplan
+    lists = [list(oplan.groups_of_wave(w, Q, nw, order)) for w in range(nw)]
+    n_it = max(len(x) for x in lists)
+    total = dup = 0
+    for i in range(n_it):
+        segs = [checksums.vector_index(x[i], j, 0, K, nv, Q=Q, order=order) // 64
+                for x in lists if i < len(x) for j in range(K)]
+        total += len(segs)
+        dup += len(segs) - len(set(segs))
+    return dup / total
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_front_duplicates_matches_brute_force(order):
+    """Against the oracle's own owners and vector map, load by load."""
+    for K, nw, Q, nv in [(3, 5, 47, 64 * 3 * 4), (2, 6, 100, 64 * 2 * 10),
+                         (1, 16, 40, 64 * 7), (4, 3, 20, 64 * 16), (3, 4, 9, 64 * 5)]:
+        assert stats.front_duplicates(order, K, nw, Q, nv, max_iters=10**6) == \
+            pytest.approx(_front_brute(order, K, nw, Q, nv), abs=0), (order, K, nw, Q, nv)
 
 
 def test_idle_slots():
