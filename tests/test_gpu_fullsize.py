@@ -158,6 +158,40 @@ def test_vector_indices_past_2_to_32(V, K):
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("size,V,K,w,L", [
+    (GIB, 16, 7, 16, 1 << 26),                        # the order row at 1 GiB
+    (128 << 20, 16, 8, 16, 1 << 26),                  # wrapped: K loads alias
+    (20 * GIB, 4, 3, 8, 20 * GIB // 4 + 64 * 3 * 999 + 5),   # indices past 2**32
+])
+def test_strided_layout_full_size(size, V, K, w, L):
+    """The strided layout in the order/footprint row's launch configuration,
+    and past 2**32 vectors: sampled waves recomputed from the seed, and the
+    cell's global sinks equal the round-robin cell's (both read the stream
+    0 .. issued - 1 modulo the allocation)."""
+    seed = sweeps.SEED_BASE + 3
+    buf = sweeps.device_buffer(size, seed)
+    try:
+        print(f"strided {size} B, V={V} K={K} w={w} L={L}", flush=True)
+        ro = recs(256 * w)
+        r = isw.sweep_plain(buf, size, K, V, w, L,
+                            isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1_NT, wave_out=ro,
+                                          order=isw.ORDER_STRIDED))
+        p = oplan.wave_group(L, K, r["waves"], order=oplan.STRIDED)
+        assert r["issued_loads"] == p["issued"]
+        rr = decode_recs(ro)
+        for wave in _sample(r["waves"], k=2 if size > GIB else 5, seed=K):
+            want = checksums.wave_from_seed(seed, V, K, p["Q"], r["waves"], wave,
+                                            buffer_bytes=size, order=oplan.STRIDED)
+            assert (rr["sum32"][wave], rr["xor32"][wave]) == want, wave
+        rb = isw.sweep_plain(buf, size, K, V, w, L,
+                             isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1_NT))
+        assert (r["sum32"], r["xor32"]) == (rb["sum32"], rb["xor32"])
+        assert r["issued_loads"] == rb["issued_loads"]
+    finally:
+        del buf
+        torch.cuda.empty_cache()
+
+
 def test_allocation_sweep_graph_full_size():
     """The allocation sweep as the bench runs it: one captured graph over
     allocation x occupancy x K x order, 16 GiB issued per cell.  512 MiB and
