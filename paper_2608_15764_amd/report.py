@@ -24,7 +24,8 @@ REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step
 # Optional sections, dropped last-first if the line would exceed the limit.
 OPTIONAL = ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
             "peak_K_at_best", "decline_2_8_at_best", "paper_like", "strict_cg",
-            "gap", "eager", "c5a", "c5b", "streaming_gate", "f4", "detail")
+            "gap", "eager", "c5a", "c5b", "streaming_gate", "f4", "f4_fixed_iters",
+            "detail")
 
 
 def _r(x, nd=4):
@@ -143,7 +144,12 @@ def compact(result, detail_path=None):
         # [saturating, rising-censored, peak-decline] curves per backend
         out["f4"] = {name: [b["counts"].get(k, 0) for k in
                             ("saturating", "rising-censored", "peak-decline")]
-                     for name, b in f4["backends"].items()}
+                     for name, b in f4["backends"].items() if "counts" in b}
+        fi = {name: [b["fixed_iters"]["counts"].get(k, 0) for k in
+                     ("saturating", "rising-censored", "peak-decline")]
+              for name, b in f4["backends"].items() if "fixed_iters" in b}
+        if fi:
+            out["f4_fixed_iters"] = fi
     sg = r.get("streaming_gate")
     if isinstance(sg, dict):
         out["streaming_gate"] = _pick(sg, ("median_gbps", "median_frac",

@@ -713,9 +713,41 @@ def order_footprint(sizes, Ks=(1, 2, 4, 8), waves_per_cu=16, L=1 << 26,
 REGIME_BACKENDS = (("hbm", GIB), ("infinity_cache", 128 * MIB), ("l2", 4 * MIB))
 
 
+REGIME_ARMS = ("fixed_work", "fixed_iters")
+
+
+def _regime_curve(buf, nbytes, V, w, g, Ks, policy, n, mode, L, iters):
+    """One response curve of the regime map: the feasible K, each timed in
+    2n launches (n passes ascending then descending after a warm-up pass),
+    or None when fewer than three K are feasible."""
+    def cell(K):
+        return isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy, mode=mode,
+                             fixed_iters=iters, grid_wgs=(g * w // 4) if g else 0)
+    keep = [K for K in Ks if _feasible(cell(K))]
+    if len(keep) < 3:
+        return None
+    seq = keep + keep[::-1]
+    arr = isw.cell_array([cell(K) for K in seq])
+    isw.sweep_run(arr, raw=True)                 # warm-up pass
+    samples = {K: [] for K in keep}
+    by_order = {"asc": {K: [] for K in keep}, "rev": {K: [] for K in keep}}
+    for _ in range(n):
+        for i, (K, r) in enumerate(zip(seq, isw.sweep_run(arr))):
+            samples[K].append(r["gbps"])
+            by_order["asc" if i < len(keep) else "rev"][K].append(r["gbps"])
+    med = stats.per_k_medians(samples)
+    return {"regime": stats.classify(med), "peak_K": stats.peak_k(med),
+            "peak_gbps": round(max(med.values()), 1),
+            "decline_2_8": (stats.decline(med[2], med[8])
+                            if 2 in med and 8 in med else None),
+            "regime_by_order": {o: stats.classify(stats.per_k_medians(v))
+                                for o, v in by_order.items()}}
+
+
 def regime_map(waves_list=(4, 8, 12, 16, 20, 24, 28, 32), widths=(4, 8, 16),
                Ks=range(1, 17), half_grid=True, backends=REGIME_BACKENDS,
-               work_bytes=GIB, policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 7):
+               work_bytes=GIB, policy=isw.CACHE_BYPASS_L1_NT, n=3, seed=SEED_BASE + 7,
+               arms=REGIME_ARMS, iters_K=8):
     """Response curves over occupancy x vector width (x full / half-CU
     grids), each classified saturating / rising-censored / peak-decline by
     the 95 % plateau rule with a three-cell tail, on every backend: a buffer
@@ -723,58 +755,54 @@ def regime_map(waves_list=(4, 8, 12, 16, 20, 24, 28, 32), widths=(4, 8, 16),
     one inside the 4 MiB L2 of an XCD (Section 4.2, "Prevalence", compares
     the prevalence of the decline on the L2-targeted and the HBM backends).
 
-    Every curve reads the same logical volume, ``work_bytes`` (half of it on
-    the half grid), wrapping over the smaller buffers.  A pass runs every K
-    ascending, then descending; after one warm-up pass ``n`` passes are
-    timed, so every cell has 2n launches, whose median is its figure."""
+    Two arms.  Fixed work: every curve reads the same logical volume,
+    ``work_bytes`` (half of it on the half grid), at every K.  Fixed
+    iterations, the sweep the paper's qualification grid ran: every K runs
+    the same iteration count, chosen so that K = ``iters_K`` reads that same
+    volume, so the volume grows with K.  Both wrap over the smaller buffers.
+    A pass runs every K ascending, then descending; after one warm-up pass
+    ``n`` passes are timed, so every cell has 2n launches, whose median is
+    its figure."""
     info = isw.sweep_device_info()
     grids = [0] + ([info["num_cus"] // 2] if half_grid else [])
     out = {}
     for name, nbytes in backends:
         buf = device_buffer(nbytes, seed)
-        curves = {}
-        counts = {"saturating": 0, "rising-censored": 0, "peak-decline": 0,
-                  "infeasible": 0}
-        for g in grids:
-            for V in widths:
-                for w in waves_list:
-                    L = work_bytes // V if g == 0 else work_bytes // (2 * V)
-                    keep = []
-                    for K in Ks:
-                        c = isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
-                                          grid_wgs=(g * w // 4) if g else 0)
-                        if _feasible(c):
-                            keep.append(K)
-                    if len(keep) < 3:
-                        counts["infeasible"] += 1
-                        continue
-                    seq = keep + keep[::-1]
-                    cells = [isw.make_cell(buf, nbytes, K, V, w, L, cache_policy=policy,
-                                           grid_wgs=(g * w // 4) if g else 0) for K in seq]
-                    arr = isw.cell_array(cells)
-                    isw.sweep_run(arr, raw=True)                 # warm-up pass
-                    samples = {K: [] for K in keep}
-                    by_order = {"asc": {K: [] for K in keep}, "rev": {K: [] for K in keep}}
-                    for _ in range(n):
-                        for i, (K, r) in enumerate(zip(seq, isw.sweep_run(arr))):
-                            samples[K].append(r["gbps"])
-                            by_order["asc" if i < len(keep) else "rev"][K].append(r["gbps"])
-                    med = stats.per_k_medians(samples)
-                    reg = stats.classify(med)
-                    counts[reg] += 1
-                    key = f"{'half' if g else 'full'}_V{V}_w{w}"
-                    curves[key] = {
-                        "regime": reg, "peak_K": stats.peak_k(med),
-                        "peak_gbps": round(max(med.values()), 1),
-                        "decline_2_8": (stats.decline(med[2], med[8])
-                                        if 2 in med and 8 in med else None),
-                        "regime_by_order": {o: stats.classify(stats.per_k_medians(v))
-                                            for o, v in by_order.items()}}
-        out[name] = {"bytes": nbytes, "counts": counts, "curves": curves,
-                     "launches_per_cell": 2 * n}
+        entry = {"bytes": nbytes, "launches_per_cell": 2 * n}
+        for arm in arms:
+            curves, iters_used = {}, {}
+            counts = {"saturating": 0, "rising-censored": 0, "peak-decline": 0,
+                      "infeasible": 0}
+            for g in grids:
+                for V in widths:
+                    for w in waves_list:
+                        curve_bytes = work_bytes if g == 0 else work_bytes // 2
+                        key = f"{'half' if g else 'full'}_V{V}_w{w}"
+                        if arm == "fixed_work":
+                            mode, L, iters = isw.FIXED_WORK, curve_bytes // V, 0
+                        else:
+                            n_waves = (g or info["num_cus"]) * w
+                            iters = max(1, curve_bytes // (V * iters_K * 64 * n_waves))
+                            mode, L = isw.FIXED_ITERS, 0
+                            iters_used[key] = iters
+                        c = _regime_curve(buf, nbytes, V, w, g, Ks, policy, n, mode, L,
+                                          iters)
+                        if c is None:
+                            counts["infeasible"] += 1
+                            continue
+                        counts[c["regime"]] += 1
+                        curves[key] = c
+            if arm == "fixed_work":
+                entry.update(counts=counts, curves=curves)
+            else:
+                entry[arm] = {"counts": counts, "curves": curves, "iters": iters_used,
+                              "iters_K": iters_K}
+        out[name] = entry
         del buf
     return {"backends": out,
-            "counts": {name: v["counts"] for name, v in out.items()},
+            "counts": {name: v["counts"] for name, v in out.items() if "counts" in v},
+            "counts_fixed_iters": {name: v["fixed_iters"]["counts"]
+                                   for name, v in out.items() if "fixed_iters" in v},
             "work_bytes": work_bytes}
 
 

@@ -623,6 +623,12 @@ def test_new_bench_rows_run_small():
     assert set(rm["backends"]) == {"a", "b"}
     for b in rm["backends"].values():
         assert sum(b["counts"].values()) == 4 and b["launches_per_cell"] == 2
+        fi = b["fixed_iters"]
+        assert sum(fi["counts"].values()) == 4
+        # K = 8 reads the fixed-work volume: 8 MiB (full grid), 4 MiB (half)
+        n_cus = isw.sweep_device_info()["num_cus"]
+        assert fi["iters"]["full_V16_w4"] == max(1, (8 << 20) // (16 * 8 * 64 * n_cus * 4))
+        assert fi["iters"]["half_V16_w8"] == max(1, (4 << 20) // (16 * 8 * 64 * n_cus // 2 * 8))
     of = sweeps.order_footprint([1 << 20, 4 << 20], Ks=(1, 2), L=1 << 17, n=1)
     assert of[4 << 20]["blocked"]["coverage"][2]["coverage"] == 0.5
     assert of[4 << 20]["strided"]["coverage"][2]["coverage"] == 0.5

@@ -89,7 +89,12 @@ def full_result():
                               "backends": {b: {"counts": {"saturating": 20,
                                                           "rising-censored": 4,
                                                           "peak-decline": 24},
-                                               "curves": regime}
+                                               "curves": regime,
+                                               "fixed_iters": {
+                                                   "counts": {"saturating": 8,
+                                                              "rising-censored": 10,
+                                                              "peak-decline": 30},
+                                                   "curves": regime}}
                                            for b in ("hbm", "infinity_cache", "l2")}},
         },
     }
@@ -122,6 +127,7 @@ def test_headline_line_fits_and_keeps_everything():
     assert d["gap"]["tail_loss"] == 0.12
     assert d["streaming_gate"]["verdict"] == "latency-bound"
     assert d["f4"] == {b: [20, 4, 24] for b in ("hbm", "infinity_cache", "l2")}
+    assert d["f4_fixed_iters"] == {b: [8, 10, 30] for b in ("hbm", "infinity_cache", "l2")}
     assert d["detail"] == "gpurun_out/bench_detail.json"
 
 
