@@ -94,7 +94,7 @@ def parse():
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
                     choices=["c3", "c4", "c5a", "c5b", "c3counters", "c2counters",
-                             "c4counters", "c4stalls", "next"],
+                             "c4counters", "c4stalls", "f3counters", "next"],
                     help="run only one extra configuration (no K sweep); "
                          "the *counters modes and c4stalls run cells one launch "
                          "per call for a separate rocprofv3 counter run")
@@ -442,6 +442,10 @@ def main():
         pols = sorted({isw.CACHE_DEFAULT, policy})
         man = sweeps.lds_counter_pass(waves_list=(1, 4), depths=(8, 16), policies=pols,
                                       manifest=a.manifest)
+        print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only == "f3counters":
+        man = sweeps.order_counter_pass(policy=policy, manifest=a.manifest)
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c2counters":

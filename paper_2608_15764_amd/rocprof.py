@@ -199,7 +199,7 @@ def attribute(rows, manifest, kernel_substr="plain_kload"):
     return out
 
 
-CELL_KEYS = ("path", "policy", "bytes", "waves_per_cu", "K", "order")
+CELL_KEYS = ("path", "policy", "bytes", "waves_per_cu", "layout", "K", "order")
 
 
 def cell_key(m):

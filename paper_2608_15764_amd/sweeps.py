@@ -1043,6 +1043,38 @@ def k_counter_pass(nbytes=GIB, waves_list=(4, 16), Ks=(1, 2, 4, 8, 16), L=1 << 2
     return order
 
 
+def order_counter_pass(sizes=(16 * MIB, 128 * MIB, GIB), waves_per_cu=16, Ks=(1, 2, 4, 8),
+                       L=1 << 26, policy=isw.CACHE_BYPASS_L1_NT, reps=3,
+                       seed=SEED_BASE + 6, manifest=None):
+    """The order/footprint cells (three address layouts) one launch per
+    call, for a separate rocprofv3 counter run: does the L2 catch the
+    repeats the lock-step sharing model counts?  The first launch of every
+    cell is its warm-up.  Returns (and optionally writes) the launch
+    manifest; each entry carries the model's share for its cell."""
+    layouts = ((isw.ORDER_ROUND_ROBIN, "round_robin"), (isw.ORDER_BLOCKED, "blocked"),
+               (isw.ORDER_STRIDED, "strided"))
+    n_waves = isw.sweep_device_info()["num_cus"] * waves_per_cu
+    order = []
+    for size in sizes:
+        buf = device_buffer(size, seed)
+        for code, name in layouts:
+            for K in Ks:
+                c = isw.make_cell(buf, size, K, 16, waves_per_cu, L, cache_policy=policy,
+                                  order=code)
+                share = stats.front_duplicates(code, K, n_waves, L // (64 * K), size // 16)
+                for rep in range(reps):
+                    r = isw.sweep_run([c])[0]
+                    order.append({"bytes": size, "waves_per_cu": waves_per_cu, "K": K,
+                                  "layout": name, "rep": rep, "warmup": rep == 0,
+                                  "front_duplicates": share,
+                                  "issued_bytes": r["issued_bytes"], "gbps": r["gbps"]})
+        del buf
+    if manifest:
+        with open(manifest, "w") as f:
+            json.dump(order, f)
+    return order
+
+
 def lds_counter_pass(nbytes=2 * GIB, waves_list=(1, 4), depths=(1, 4, 8, 16),
                      L=1 << 27, policy=isw.CACHE_DEFAULT, reps=3,
                      seed=SEED_BASE + 3, manifest=None, policies=None):

@@ -629,6 +629,11 @@ def test_new_bench_rows_run_small():
         n_cus = isw.sweep_device_info()["num_cus"]
         assert fi["iters"]["full_V16_w4"] == max(1, (8 << 20) // (16 * 8 * 64 * n_cus * 4))
         assert fi["iters"]["half_V16_w8"] == max(1, (4 << 20) // (16 * 8 * 64 * n_cus // 2 * 8))
+    man = sweeps.order_counter_pass(sizes=(1 << 20,), Ks=(1, 2), L=1 << 17, reps=2,
+                                    waves_per_cu=4)
+    assert len(man) == 3 * 2 * 2 and sum(m["warmup"] for m in man) == 6
+    assert {m["layout"] for m in man} == {"round_robin", "blocked", "strided"}
+    assert all(m["issued_bytes"] == 16 * (1 << 17) for m in man)
     of = sweeps.order_footprint([1 << 20, 4 << 20], Ks=(1, 2), L=1 << 17, n=1)
     assert of[4 << 20]["blocked"]["coverage"][2]["coverage"] == 0.5
     assert of[4 << 20]["strided"]["coverage"][2]["coverage"] == 0.5
