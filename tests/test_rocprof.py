@@ -154,3 +154,20 @@ def test_cell_table_keys_on_policy_and_derives_latencies(tmp_path):
     row = tab[("lds_matched", "default", 1 << 31, 1, 8, "asc")]
     assert row["tcp_tcc_read_latency"] == pytest.approx(900.0)
     assert "tcp_wave_latency" not in row           # zero state reads: no ratio
+
+
+def test_cell_table_keys_on_layout(tmp_path):
+    """Order/footprint manifests name the address layout: cells of equal
+    size, occupancy and K but different layouts stay apart."""
+    K2 = "void ilp::plain_kload<2, 16, 3>(ilp::PlainArgs)"
+    man, rows = [], []
+    for layout, hits in (("round_robin", 10.0), ("strided", 50.0)):
+        for rep in range(3):
+            man.append({"bytes": 128 << 20, "waves_per_cu": 16, "K": 2, "layout": layout,
+                        "rep": rep, "warmup": rep == 0})
+            rows.append((K2, "TCC_HIT_sum", hits + rep))
+    p = tmp_path / "d_counter_collection.csv"
+    _write_cc(p, rows)
+    tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man)
+    assert set(tab) == {(128 << 20, 16, "round_robin", 2), (128 << 20, 16, "strided", 2)}
+    assert tab[(128 << 20, 16, "strided", 2)]["TCC_HIT_sum"] == 51.5
