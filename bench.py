@@ -592,6 +592,7 @@ def main():
         # the same gate form with 16-byte loads: four times the bytes in flight
         result["streaming_gate_16B"] = sweeps.streaming_gate(buf, nbytes, vec_width=16,
                                                              latency_ns=lat)
+        result["library_reads"] = library_reads(buf, nbytes)
     if not a.no_cpu_baseline:
         ks_best = sorted({m["K"] for m in meta if m["waves_per_cu"] == best_w})
         result["cpu_baseline"] = cpu_baseline(seed, nbytes, L, ks_best, best_w, buf,
@@ -609,6 +610,41 @@ def main():
     detail = a.json_out or os.path.join("gpurun_out", "bench_detail.json")
     report.emit(result, detail, sys.stdout)
     return 0
+
+
+def library_reads(buf, nbytes, reps=10):
+    """Context for the roofline, not part of the path: the rate of torch's
+    own kernels over the same resident 1 GiB buffer, each timed with a
+    hipEvent pair on torch's current stream (the one they run on), median
+    of ``reps`` after a warm-up.  Reductions read the buffer once; the
+    device copy reads it and writes as many bytes."""
+    import torch
+    x = buf.view(torch.int32)[: nbytes // 4]
+    y = torch.empty_like(x)
+    xf = x.view(torch.float32)
+    ops = {"sum_float32": (lambda: xf.sum(), nbytes),
+           "sum_int32_to_int64": (lambda: x.sum(dtype=torch.int64), nbytes),
+           "amax_int32": (lambda: torch.amax(x), nbytes),
+           "copy_read_plus_write": (lambda: y.copy_(x), 2 * nbytes)}
+    out = {}
+    for name, (fn, moved) in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = sorted(ms)[len(ms) // 2]
+        out[name] = {"bytes_moved": moved, "median_ms": round(med, 4),
+                     "gbps": round(moved / (med * 1e6), 1),
+                     "frac_of_hbm_peak": round(moved / (med * 1e6) / 8000.0, 4)}
+    del y
+    return out
 
 
 def run_extras(a, isw, sweeps, only=None, best_w=None):
