@@ -388,8 +388,9 @@ int sweep_batched(const sweep_cell_t* cells, int n, const sweep_opts_t* opt,
  * cells' buffers must stay allocated until the graph is destroyed; their
  * contents may change between replays.
  * sweep_graph_create: validates every cell (errors as sweep_run), captures
- *   and instantiates; *out receives the handle.  Only opt->pin_occupancy is
- *   read (opt may be NULL).  SWEEP_ENOMEM if the scratch cannot be had.
+ *   and instantiates; *out receives the handle.  Only opt->pin_occupancy
+ *   and opt->fuse are read (opt may be NULL).  SWEEP_ENOMEM if the scratch
+ *   cannot be had.
  * sweep_graph_launch: replays on `stream` (a hipStream_t of the graph's
  *   device, NULL = default stream), waits, and fills results[0..n) in cell
  *   order (per-cell windows from the in-kernel clock records, event_ms 0)

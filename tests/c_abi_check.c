@@ -1,9 +1,10 @@
 /* Plain-C user of the C ABI: no torch, no Python.  Allocates a buffer with
  * the HIP runtime, fills it with the seeded generator, runs one plain-load
- * cell, one LDS-direct cell, one graph-batched pair and two replays of a
- * captured graph (the buffer refilled with seed + 1 between them), and prints the
- * global sinks as "name sum xor issued" lines for the calling test to check
- * against the oracle. */
+ * cell in each address order, the allocation-free entry point, one
+ * LDS-direct cell, one graph-batched pair, two replays of a captured graph
+ * (the buffer refilled with seed + 1 between them), one fused graph and a
+ * split two-stream launch, and prints the global sinks as "name sum xor
+ * issued" lines for the calling test to check against the oracle. */
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -35,6 +36,15 @@ int main(int argc, char** argv) {
   sweep_result_t r;
   CHECK(sweep_plain(buf, bytes, 4, 16, 16, bytes / 16, &opt, &r));
   printf("plain %u %u %llu\n", r.sum32, r.xor32, (unsigned long long)r.issued_loads);
+  opt.order = SWEEP_ORDER_BLOCKED;
+  CHECK(sweep_plain(buf, bytes, 3, 16, 8, bytes / 16, &opt, &r));
+  printf("blocked_K3 %u %u %llu\n", r.sum32, r.xor32, (unsigned long long)r.issued_loads);
+  opt.order = SWEEP_ORDER_STRIDED;
+  CHECK(sweep_plain(buf, bytes, 3, 16, 8, bytes / 16, &opt, &r));
+  printf("strided_K3 %u %u %llu\n", r.sum32, r.xor32, (unsigned long long)r.issued_loads);
+  opt.order = SWEEP_ORDER_ROUND_ROBIN;
+  CHECK(sweep_plain_noalloc(buf, bytes, 4, 16, 16, bytes / 16, &opt, &r));
+  printf("noalloc %u %u %llu\n", r.sum32, r.xor32, (unsigned long long)r.issued_loads);
   CHECK(sweep_lds_async(buf, bytes, 8, 16, 4, bytes / 16, &opt, &r));
   printf("lds_async %u %u %llu\n", r.sum32, r.xor32, (unsigned long long)r.issued_loads);
 
@@ -66,6 +76,17 @@ int main(int argc, char** argv) {
              (unsigned long long)rs[i].issued_loads);
   }
   CHECK(sweep_graph_destroy(g));
+  /* two cells of one configuration fused into one persistent launch */
+  sweep_cell_t fc[2] = {cells[1], cells[1]};
+  opt.fuse = 1;
+  g = NULL;
+  CHECK(sweep_graph_create(fc, 2, &opt, &g));
+  CHECK(sweep_graph_launch(g, NULL, rs, &ms));
+  for (int i = 0; i < 2; ++i)
+    printf("fused_%d %u %u %llu\n", i, rs[i].sum32, rs[i].xor32,
+           (unsigned long long)rs[i].issued_loads);
+  CHECK(sweep_graph_destroy(g));
+  opt.fuse = 0;
   /* the two streams on different CUs, over the buffer's two halves */
   sweep_result_t r2[2];
   CHECK(sweep_two_stream_split(buf, bytes, 4, 8, 8, SWEEP_KIND_PLAIN, bytes / 16, &opt, r2));

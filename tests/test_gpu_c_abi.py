@@ -38,9 +38,16 @@ def test_plain_c_program(tmp_path):
     words = splitmix.buffer_words(seed, nbytes)
     whole = checksums.whole_buffer(words)
     L = nbytes // 16
-    for name, K in (("plain", 4), ("lds_async", 8), ("batched_K2", 2)):
+    for name, K in (("plain", 4), ("lds_async", 8), ("batched_K2", 2), ("noalloc", 4)):
         assert res[name][:2] == whole and res[name][2] == L, name
     from paper_2608_15764_amd import ilpsweep as isw
+    # K = 3 does not divide the pass: every order reads the same prefix
+    nw8 = isw.sweep_device_info()["num_cus"] * 8
+    p3 = oplan.wave_group(L, 3, nw8)
+    for name, order in (("blocked_K3", oplan.BLOCKED), ("strided_K3", oplan.STRIDED)):
+        want = checksums.combine(*checksums.per_wave(words, 16, 3, p3["Q"], nw8,
+                                                     order=order))
+        assert res[name] == (*want, p3["issued"]), name
     n_waves = isw.sweep_device_info()["num_cus"] * 32
     p = oplan.wave_group(L, 3, n_waves)
     want = checksums.combine(*checksums.per_wave(words, 16, 3, p["Q"], n_waves))
@@ -52,6 +59,8 @@ def test_plain_c_program(tmp_path):
     assert res["graph_K2_rep1"] == (*checksums.whole_buffer(words1), L)
     want1 = checksums.combine(*checksums.per_wave(words1, 16, 3, p["Q"], n_waves))
     assert res["graph_K3_rep1"] == (*want1, p["issued"])
+    # the fused graph ran after the refill: both points equal the unfused cell
+    assert res["fused_0"] == res["fused_1"] == res["graph_K3_rep1"]
     # split two-stream launch over the refilled buffer: each stream reads
     # its whole half exactly once
     (a0, an), (b0, bn) = checksums.two_stream_regions(L)
