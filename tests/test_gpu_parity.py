@@ -74,6 +74,48 @@ PLAIN_CASES = [
 ]
 
 
+def _random_plain_cases(n=48, seed=20261203):
+    """Seeded random cells: width, K, occupancy, explicit grid, allocation
+    (whole 64-vector segments), a target with a ragged remainder, address
+    order and cache policy; the volume wraps the allocation in most."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        V = int(rng.choice([4, 8, 16]))
+        K = int(rng.integers(1, 17))
+        w = int(rng.choice([4, 8, 12, 16, 20, 24, 28, 32]))
+        grid = int(rng.integers(1, 7))
+        n_vec = 64 * int(rng.integers(1, 201))
+        Q = int(rng.integers(1, 301))
+        L = 64 * K * Q + int(rng.integers(0, 64 * K))
+        out.append((V, K, w, grid, n_vec, L, int(rng.integers(0, 3)), int(rng.integers(0, 4))))
+    return out
+
+
+@pytest.mark.parametrize("V,K,w,grid,n_vec,L,order,policy", _random_plain_cases())
+def test_plain_random_cells_match_oracle(V, K, w, grid, n_vec, L, order, policy):
+    """Per lane, per wave and global sinks against the oracle."""
+    nbytes = n_vec * V
+    buf = synth.random_bytes(nbytes, seed=n_vec + K + 7 * V, device="cuda")
+    n_waves = grid * 4
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=policy, lane_out=lo,
+                         wave_out=ro, order=order)
+    r = isw.sweep_plain(buf, nbytes, K, V, w, L, opts)
+    p = oplan.wave_group(L, K, n_waves, order=order)
+    assert r["issued_loads"] == p["issued"]
+    assert (r["iters_min"], r["iters_max"]) == (p["iters_min"], p["iters_max"])
+    words = host_words(buf)
+    ws, wx = checksums.per_lane(words, V, K, p["Q"], n_waves, order=order)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    rr = decode_recs(ro)
+    os_, ox = checksums.per_wave(words, V, K, p["Q"], n_waves, order=order)
+    assert np.array_equal(rr["sum32"], os_) and np.array_equal(rr["xor32"], ox)
+    assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
+
+
 @pytest.mark.parametrize("policy", [0, 1, 2, 3])
 @pytest.mark.parametrize("V,K,w,grid,n_vec,L", PLAIN_CASES)
 def test_plain_matches_oracle(V, K, w, grid, n_vec, L, policy):
