@@ -31,6 +31,8 @@
  *    coalesced 64-lane segment of 64 * vec_width bytes.  Lane l of load j of
  *    wave-group q reads vector ((q*K + j)*64 + l) mod (bytes / vec_width).
  *    Wave w of the grid handles q = w, w + n_waves, ... (round robin).
+ *    This is the default order; opts.order selects the blocked deal or the
+ *    strided layout for the plain kernel (SWEEP_ORDER_*).
  *  - Sinks: per lane a wrapping 32-bit sum and a 32-bit XOR of every loaded
  *    word, reduced over lanes, waves and the grid with the same operators.
  *  - Bandwidth is issued logical bytes per calibrated nanosecond, in decimal
