@@ -731,6 +731,9 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
         t = time.perf_counter()
         rows["f1_latency_ladder"] = sweeps.latency_ladder()
         rows["f1_latency_ladder"]["wall_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        rows["f1_latency_by_xcd"] = sweeps.latency_by_xcd()
+        rows["f1_latency_by_xcd"]["wall_s"] = time.perf_counter() - t
     return rows
 
 

@@ -207,6 +207,16 @@ typedef struct {
   double   shader_clock_hz;  /* shader clock measured in the same window    */
 } sweep_chase_t;
 
+/* One walker of sweep_chase_walkers. */
+typedef struct {
+  uint32_t final_index;      /* index reached after warm + timed hops       */
+  uint32_t xcc_id;           /* XCD the walker ran on (0..7 on MI355X)       */
+  uint32_t hops;             /* timed hops                                   */
+  uint32_t reserved;
+  uint64_t wall_ticks;       /* device wall-clock ticks over the timed hops  */
+  double   ns_per_hop;       /* mean latency of one dependent load           */
+} sweep_walker_t;
+
 /* Initialise the library on HIP device `ordinal` (makes it current) and
  * allocate its scratch.  Optional: every other call initialises lazily on
  * the current device.  Errors: SWEEP_ENODEV, SWEEP_EHIP, SWEEP_ENOMEM. */
@@ -464,6 +474,23 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
                 uint32_t warm_hops, uint32_t hops, int cache_policy,
                 uint32_t* samples, uint32_t n_samples, void* stream,
                 sweep_chase_t* out);
+
+/* Dependent-chain walkers on several XCDs at once: the latency probe of
+ * Section 4.1 resolved by XCD.  The paper's probe ran on one SM, so it
+ * could not separate near and far paths; on MI355X every XCD has its own
+ * L2 and its own route to the shared last-level cache and HBM.
+ * Launches `n_walkers` workgroups of one wave; lane 0 of workgroup b
+ * follows the chain from starts[b] (host array of n_walkers word indices)
+ * for `warm_hops` untimed and `hops` timed dependent loads, as sweep_chase
+ * does without samples.  The dispatcher deals workgroups to the XCDs in
+ * turn; out[b].xcc_id is the XCD walker b ran on (HW_REG_XCC_ID).  With
+ * the walkers spread along the chain they touch different lines, and with
+ * at most 64 loads in flight the memory system is unloaded.
+ *   n_walkers  1..64;  out: host array of n_walkers results
+ * Synchronous on `stream`.  Errors: SWEEP_EINVAL, SWEEP_EALIGN, SWEEP_EHIP. */
+int sweep_chase_walkers(const void* chain, size_t bytes, const uint32_t* starts,
+                        int n_walkers, uint32_t warm_hops, uint32_t hops,
+                        int cache_policy, void* stream, sweep_walker_t* out);
 
 /* Text of an error code. */
 const char* sweep_strerror(int code);

@@ -108,6 +108,20 @@ struct ChaseArgs {
   uint64_t* out;           // device [5]
 };
 
+// Several dependent-chain walkers at once, one single-lane wave per
+// workgroup; walker b starts at starts[b] and writes out[4b .. 4b+3] =
+// final index, wall clock at the start and end of its timed hops, XCC_ID.
+constexpr uint32_t kMaxWalkers = 64;
+struct WalkArgs {
+  const uint32_t* buf;
+  uint32_t n_bytes;        // buffer bytes (< 4 GiB)
+  uint32_t warm;           // untimed hops per walker
+  uint32_t steps;          // timed hops per walker
+  uint32_t n_walkers;      // 1..kMaxWalkers (= the grid)
+  uint32_t starts[kMaxWalkers];
+  uint64_t* out;           // device [4 * n_walkers]
+};
+
 // Per-cell result reduced on the device from the wave records.
 struct CellRes {
   uint64_t sum;   // low 32 bits used
@@ -145,6 +159,7 @@ const void* two_stream_kernel(int D, int policy);
 // ---- pointer chase (kernels_chase.hip)
 const void* chase_kernel(int policy);
 hipError_t launch_chase(int policy, hipStream_t st, const ChaseArgs& a);
+hipError_t launch_walkers(int policy, hipStream_t st, const WalkArgs& a);
 
 // ---- fill, finishing, clock, reduction (kernels_misc.hip)
 hipError_t launch_fill(uint32_t* buf, uint64_t n_words, uint64_t seed,

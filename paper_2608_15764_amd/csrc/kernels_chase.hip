@@ -52,6 +52,29 @@ __global__ __launch_bounds__(64) void chase(ChaseArgs a) {
   a.out[4] = m1;
 }
 
+// Walker b of the grid follows the chain from starts[b]: one dependent load
+// in flight per walker, every walker on its own workgroup, so the
+// dispatcher places them on the XCDs in turn and each reports its own.
+template <int POL>
+__global__ __launch_bounds__(64) void chase_walkers(WalkArgs a) {
+  if (threadIdx.x != 0) return;
+  const uint32_t b = blockIdx.x;
+  uint32_t idx = a.starts[b];
+#pragma unroll 1
+  for (uint32_t i = 0; i < a.warm; ++i) idx = chase_load<POL>(a.buf, a.n_bytes, idx);
+  wait_vmcnt<0>();
+  const uint64_t r0 = wall_ticks();
+#pragma unroll 1
+  for (uint32_t i = 0; i < a.steps; ++i) idx = chase_load<POL>(a.buf, a.n_bytes, idx);
+  wait_vmcnt<0>();
+  const uint64_t r1 = wall_ticks();
+  uint64_t* o = a.out + 4u * b;
+  o[0] = idx;
+  o[1] = r0;
+  o[2] = r1;
+  o[3] = xcc_id_reg();
+}
+
 const void* chase_kernel(int policy) {
   switch (policy) {
     case SWEEP_CACHE_DEFAULT: return reinterpret_cast<const void*>(&chase<SWEEP_CACHE_DEFAULT>);
@@ -60,6 +83,20 @@ const void* chase_kernel(int policy) {
     case SWEEP_CACHE_BYPASS_L1_NT: return reinterpret_cast<const void*>(&chase<SWEEP_CACHE_BYPASS_L1_NT>);
     default: return nullptr;
   }
+}
+
+hipError_t launch_walkers(int policy, hipStream_t st, const WalkArgs& a) {
+  const void* fn = nullptr;
+  switch (policy) {
+    case SWEEP_CACHE_DEFAULT: fn = reinterpret_cast<const void*>(&chase_walkers<SWEEP_CACHE_DEFAULT>); break;
+    case SWEEP_CACHE_NT: fn = reinterpret_cast<const void*>(&chase_walkers<SWEEP_CACHE_NT>); break;
+    case SWEEP_CACHE_BYPASS_L1: fn = reinterpret_cast<const void*>(&chase_walkers<SWEEP_CACHE_BYPASS_L1>); break;
+    case SWEEP_CACHE_BYPASS_L1_NT: fn = reinterpret_cast<const void*>(&chase_walkers<SWEEP_CACHE_BYPASS_L1_NT>); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (a.n_walkers == 0 || a.n_walkers > kMaxWalkers) return hipErrorInvalidValue;
+  void* args[] = {const_cast<WalkArgs*>(&a)};
+  return hipLaunchKernel(fn, dim3(a.n_walkers), dim3(64), args, 0, st);
 }
 
 hipError_t launch_chase(int policy, hipStream_t st, const ChaseArgs& a) {

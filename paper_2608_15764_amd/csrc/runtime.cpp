@@ -63,6 +63,7 @@ struct Dev {
   double* dsum_h = nullptr;
   uint64_t* clk = nullptr;
   uint64_t* chase_out = nullptr;  // 5 words per chase call
+  uint64_t* walk_out = nullptr;   // 4 words per walker
   uint64_t* offs = nullptr;     // per-cell record offsets (device)
   size_t offs_cap = 0;
   uint64_t* offs_h = nullptr;   // pinned staging copy
@@ -130,6 +131,7 @@ void release_device(Dev* d) {
   if (d->dsum_h) (void)hipHostFree(d->dsum_h);
   if (d->clk) (void)hipFree(d->clk);
   if (d->chase_out) (void)hipFree(d->chase_out);
+  if (d->walk_out) (void)hipFree(d->walk_out);
   if (d->offs) (void)hipFree(d->offs);
   if (d->offs_h) (void)hipHostFree(d->offs_h);
   for (auto e : d->ev) (void)hipEventDestroy(e);
@@ -149,6 +151,8 @@ int setup_device(Dev* d) {
   SW_TRY(ensure_dev(d->clk, clk_cap, 1));
   size_t chase_cap = 0;
   SW_TRY(ensure_dev(d->chase_out, chase_cap, 5));
+  size_t walk_cap = 0;
+  SW_TRY(ensure_dev(d->walk_out, walk_cap, 4 * (size_t)kMaxWalkers));
   SW_TRY(ensure_events(*d, 8));
   d->scratch_ready = true;
   return SWEEP_OK;
@@ -1157,6 +1161,52 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
   o.ns_per_hop = secs * 1e9 / hops;
   o.shader_clock_hz = secs > 0 ? (double)(h[4] - h[3]) / secs : 0.0;
   *out = o;
+  return SWEEP_OK;
+}
+
+int sweep_chase_walkers(const void* chain, size_t bytes, const uint32_t* starts,
+                        int n_walkers, uint32_t warm_hops, uint32_t hops, int cache_policy,
+                        void* stream, sweep_walker_t* out) {
+  if (!out || !chain || !starts) return fail(SWEEP_EINVAL, "NULL argument");
+  if (n_walkers < 1 || n_walkers > (int)kMaxWalkers)
+    return fail(SWEEP_EINVAL, "n_walkers must be 1..64");
+  if (bytes == 0 || bytes >= (1ull << 32)) return fail(SWEEP_EINVAL, "chain must be below 4 GiB");
+  if (bytes % 4 || reinterpret_cast<uintptr_t>(chain) % 16)
+    return fail(SWEEP_EALIGN, "chain must be 16-byte aligned and whole words");
+  for (int i = 0; i < n_walkers; ++i)
+    if (starts[i] >= bytes / 4) return fail(SWEEP_EINVAL, "start index outside the chain");
+  if (cache_policy < 0 || cache_policy > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
+  if (hops == 0) return fail(SWEEP_EINVAL, "no timed hops");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
+  WalkArgs a{};
+  a.buf = static_cast<const uint32_t*>(chain);
+  a.n_bytes = (uint32_t)bytes;
+  a.warm = warm_hops;
+  a.steps = hops;
+  a.n_walkers = (uint32_t)n_walkers;
+  std::copy(starts, starts + n_walkers, a.starts);
+  a.out = d->walk_out;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t h[4 * kMaxWalkers];
+  hipError_t e = launch_walkers(cache_policy, st, a);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h, d->walk_out, 4 * sizeof(uint64_t) * (size_t)n_walkers,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(SWEEP_EHIP, std::string("walkers: ") + hipGetErrorString(e));
+  for (int i = 0; i < n_walkers; ++i) {
+    const uint64_t* w = h + 4 * i;
+    sweep_walker_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.final_index = (uint32_t)w[0];
+    o.xcc_id = (uint32_t)(w[3] & 0xF);
+    o.hops = hops;
+    o.wall_ticks = w[2] >= w[1] ? w[2] - w[1] : 0;
+    o.ns_per_hop = (double)o.wall_ticks / d->hz() * 1e9 / hops;
+    out[i] = o;
+  }
   return SWEEP_OK;
 }
 

@@ -90,6 +90,15 @@ class sweep_chase_t(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class sweep_walker_t(C.Structure):
+    _fields_ = [("final_index", C.c_uint32), ("xcc_id", C.c_uint32),
+                ("hops", C.c_uint32), ("reserved", C.c_uint32),
+                ("wall_ticks", C.c_uint64), ("ns_per_hop", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 class sweep_cell_t(C.Structure):
     _fields_ = [("kind", C.c_int), ("K", C.c_int), ("vec_width", C.c_int),
                 ("waves_per_cu", C.c_int), ("cache_policy", C.c_int),
@@ -155,6 +164,9 @@ _SIG = {
     "sweep_chase": (C.c_int, [_P, C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint32,
                               C.c_int, _P, C.c_uint32, _P,
                               C.POINTER(sweep_chase_t)]),
+    "sweep_chase_walkers": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint32), C.c_int,
+                                      C.c_uint32, C.c_uint32, C.c_int, _P,
+                                      C.POINTER(sweep_walker_t)]),
     "sweep_strerror": (C.c_char_p, [C.c_int]),
     "sweep_last_error": (C.c_char_p, []),
     "sweep_version": (C.c_char_p, []),
@@ -470,6 +482,22 @@ def sweep_chase(chain, bytes_, start, warm_hops, hops, cache_policy=CACHE_DEFAUL
                            cache_policy, _ptr(samples), n_samples,
                            _stream(stream), C.byref(o)), "sweep_chase")
     return o.as_dict()
+
+
+MAX_WALKERS = 64
+
+
+def sweep_chase_walkers(chain, bytes_, starts, warm_hops, hops, cache_policy=CACHE_DEFAULT,
+                        stream=None):
+    """One dependent-chain walker per start index, all at once; returns one
+    dict per walker (final index, the XCD it ran on, ns per hop)."""
+    n = len(starts)
+    st = (C.c_uint32 * max(n, 1))(*[int(v) for v in starts])
+    out = (sweep_walker_t * max(n, 1))()
+    _check(lib.sweep_chase_walkers(_ptr(chain), bytes_, st, n, warm_hops, hops,
+                                   cache_policy, _stream(stream), out),
+           "sweep_chase_walkers")
+    return [out[i].as_dict() for i in range(n)]
 
 
 def sweep_strerror(code):

@@ -863,6 +863,51 @@ def latency_ladder(footprints=None, stride=128, hops=8192, n_samples=4096,
     return out
 
 
+XCD_FOOTPRINTS = (("l2", 1 * MIB), ("infinity_cache", 64 * MIB), ("hbm", 2 * GIB))
+
+
+def latency_by_xcd(footprints=XCD_FOOTPRINTS, walkers=(8, 64), hops=4096, stride=128,
+                   policy=isw.CACHE_BYPASS_L1, seed=SEED_BASE + 9, evict_bytes=2 * GIB):
+    """Unloaded dependent-load latency resolved by XCD (the latency ladder of
+    Section 4.1 run from every XCD at once): ``n`` walkers spread evenly
+    along one chain, one per workgroup, so the dispatcher puts n / 8 on each
+    XCD.  Cache-resident footprints are warmed by every walker walking the
+    whole cycle first (each XCD's L2 then holds what fits); the HBM one is
+    measured cold after a 2 GiB eviction stream.  Per footprint and walker
+    count: mean ns per hop on each XCD, the spread across XCDs, and the odd
+    minus even XCD means."""
+    import synth
+    evict_buf = device_buffer(evict_bytes, seed + 1)
+    out = {}
+    for name, fp in footprints:
+        nodes = fp // stride
+        cold = fp > stats.INFINITY_CACHE_BYTES
+        row = {}
+        for n in walkers:
+            chain, starts = synth.chase_chain_starts(fp, stride, seed + fp.bit_length(), n,
+                                                     device="cuda")
+            if cold:
+                isw.sweep_plain(evict_buf, evict_bytes, 4, 16, 32, evict_bytes // 16)
+            warm = 0 if cold else nodes
+            res = isw.sweep_chase_walkers(chain, fp, starts, warm, hops, policy)
+            by = {}
+            for r in res:
+                by.setdefault(r["xcc_id"], []).append(r["ns_per_hop"])
+            per = {x: sum(v) / len(v) for x, v in sorted(by.items())}
+            odd = [v for x, v in per.items() if x % 2]
+            even = [v for x, v in per.items() if not x % 2]
+            row[n] = {"per_xcd_ns": {x: round(v, 2) for x, v in per.items()},
+                      "walkers_per_xcd": {x: len(v) for x, v in sorted(by.items())},
+                      "spread": round(max(per.values()) / min(per.values()) - 1, 4),
+                      "odd_minus_even_ns": (round(sum(odd) / len(odd) - sum(even) / len(even), 2)
+                                            if odd and even else None),
+                      "cold": cold, "warm_hops": warm}
+            del chain
+        out[name] = {"bytes": fp, "walkers": row}
+    del evict_buf
+    return out
+
+
 # ------------------------------- baseline arm and streaming gate (Table 1)
 def fixed_iteration_arm(buf, nbytes, Ks=(1, 2, 4, 8), waves_per_cu=16, iters=None,
                         policy=isw.CACHE_BYPASS_L1_NT, n=3):

@@ -52,8 +52,7 @@ def normal_payload(kind, n, seed, device="cpu", chunk=1 << 26):
     return out
 
 
-def chase_chain(footprint, stride, seed, device="cpu"):
-    """(uint8 tensor of ``footprint`` bytes, start word index)."""
+def _chase_cycle(footprint, stride, seed, device):
     if footprint % stride or stride % 4:
         raise ValueError("footprint must be a multiple of stride, stride of 4")
     n = footprint // stride
@@ -63,4 +62,22 @@ def chase_chain(footprint, stride, seed, device="cpu"):
     words = torch.zeros(footprint // 4, dtype=torch.int32, device=device)
     nxt = torch.roll(order, -1)
     words[order * step] = (nxt * step).to(torch.int32)
-    return words.view(torch.uint8), int(order[0].item()) * step
+    return words.view(torch.uint8), order, step
+
+
+def chase_chain(footprint, stride, seed, device="cpu"):
+    """(uint8 tensor of ``footprint`` bytes, start word index): one cycle
+    through every ``stride``-byte node in random order."""
+    words, order, step = _chase_cycle(footprint, stride, seed, device)
+    return words, int(order[0].item()) * step
+
+
+def chase_chain_starts(footprint, stride, seed, n_starts, device="cpu"):
+    """The same chain as ``chase_chain`` and ``n_starts`` word indices spread
+    evenly along its cycle (start i is i * nodes / n_starts hops on)."""
+    words, order, step = _chase_cycle(footprint, stride, seed, device)
+    n = order.numel()
+    if not 1 <= n_starts <= n:
+        raise ValueError("n_starts must be 1..nodes")
+    starts = [int(order[(i * n) // n_starts].item()) * step for i in range(n_starts)]
+    return words, starts

@@ -61,6 +61,7 @@ STRUCTS = {
                        "mem_clock_khz", "mem_bus_bits"],
     "sweep_chase_t": ["final_index", "hops", "wall_ticks", "ns_per_hop",
                       "shader_clock_hz"],
+    "sweep_walker_t": ["final_index", "xcc_id", "hops", "wall_ticks", "ns_per_hop"],
     "sweep_cell_t": ["kind", "K", "vec_width", "waves_per_cu", "cache_policy",
                      "mode", "fixed_iters", "grid_wgs", "buf", "bytes",
                      "total_logical_loads", "order"],

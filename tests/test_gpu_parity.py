@@ -544,6 +544,39 @@ def test_chase_rejects_bad_arguments():
         assert e.value.code == isw.EINVAL
 
 
+@pytest.mark.parametrize("policy", [0, 2, 3])
+@pytest.mark.parametrize("n_walkers,footprint,warm,hops", [(1, 8192, 10, 300),
+                                                          (8, 1 << 20, 100, 500),
+                                                          (64, 1 << 20, 0, 700),
+                                                          (37, 1 << 16, 512, 1000)])
+def test_walkers_match_oracle(n_walkers, footprint, warm, hops, policy):
+    """Every walker lands where the oracle's walk from its start lands, and
+    reports a valid XCD; walkers wrap the cycle when warm + hops exceeds it."""
+    from oracle import chase
+    chain, starts = synth.chase_chain_starts(footprint, 128, footprint + n_walkers,
+                                             n_walkers, device="cuda")
+    print(f"walkers {n_walkers} over {footprint} B, warm {warm}, hops {hops}", flush=True)
+    out = isw.sweep_chase_walkers(chain, footprint, starts, warm, hops, policy)
+    words = host_words(chain)
+    assert len(out) == n_walkers
+    n_xcc = isw.sweep_device_info()["num_cus"] // 32
+    for s0, r in zip(starts, out):
+        assert r["final_index"] == chase.follow(words, s0, warm + hops)
+        assert r["hops"] == hops and r["ns_per_hop"] > 0
+        assert r["xcc_id"] < max(n_xcc, 1)
+    if n_walkers >= 8:
+        # workgroups are dealt to the XCDs in turn
+        assert len({r["xcc_id"] for r in out}) == min(n_walkers, max(n_xcc, 1))
+
+
+def test_walkers_reject_bad_arguments():
+    chain, starts = synth.chase_chain_starts(4096, 64, 1, 4, device="cuda")
+    for st, hops in [([], 10), (list(range(65)), 10), ([4096 // 4], 10), (starts, 0)]:
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_chase_walkers(chain, 4096, st, 0, hops)
+        assert e.value.code == isw.EINVAL
+
+
 @pytest.mark.parametrize("V,K,n_vec,L", [(16, 4, 64, 64 * 4 * 3),      # one segment
                                          (4, 1, 256, 64 * 5),           # Q < waves
                                          (16, 16, 64, 64 * 16),         # one group

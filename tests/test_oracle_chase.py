@@ -27,3 +27,18 @@ def test_follow_by_hand():
     assert [chase.follow(words, 0, h) for h in range(6)] == [0, 2, 3, 1, 0, 2]
     assert chase.cycle_length(words, 0, 10) == 4
     assert chase.cycle_length(np.array([1, 1], dtype=np.uint32), 0, 5) is None
+
+
+@pytest.mark.parametrize("n_starts", [1, 3, 8, 64])
+def test_chain_starts_are_evenly_spaced_along_the_cycle(n_starts):
+    """Start i is i * nodes / n_starts hops from start 0 along the cycle,
+    and the chain is the one chase_chain builds from the same seed."""
+    t, s0 = synth.chase_chain(8192, 128, seed=9)
+    t2, starts = synth.chase_chain_starts(8192, 128, 9, n_starts)
+    words = t.numpy().view(np.uint32)
+    assert np.array_equal(words, t2.numpy().view(np.uint32)) and starts[0] == s0
+    n = 8192 // 128
+    for i, s in enumerate(starts):
+        assert chase.follow(words, s0, (i * n) // n_starts) == s
+    with pytest.raises(ValueError):
+        synth.chase_chain_starts(8192, 128, 9, n + 1)
