@@ -202,3 +202,43 @@ def test_fused_batch_keeps_the_K_load_loop(fused, K, V, P):
     m = _meta(text, name)
     assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0
     assert m["private_segment_fixed_size"] == 0
+
+
+def _loops(lines):
+    """Every loop (header label to back-branch), in program order."""
+    out = []
+    for i, l in enumerate(lines):
+        if "Loop Header" in l:
+            label = l.split(":")[0]
+            body = []
+            for l2 in lines[i + 1:]:
+                body.append(l2)
+                if re.match(r"s_cbranch_\w+\s+" + re.escape(label) + r"\b", l2):
+                    out.append(body)
+                    break
+    return out
+
+
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", ["chase", "chase_walkers"])
+def test_chase_loops_keep_one_dependent_load_in_flight(kernel, P):
+    """Every hop loop of the latency probes issues exactly one load and
+    waits for the previous one before it (the address depends on it), and
+    stores nothing: one dependent load in flight, so the time per hop is the
+    load-to-use latency."""
+    t = _asm("kernels_chase")
+    fns = _functions(t)
+    args = "ChaseArgs" if kernel == "chase" else "WalkArgs"
+    name = f"_ZN3ilp{len(kernel)}{kernel}ILi{P}EEEvNS_{len(args)}{args}E"
+    assert name in fns, sorted(fns)
+    # the hop loops (the sampled probe also has a loop copying its samples
+    # out of LDS, which loads nothing from memory)
+    loops = [b for b in _loops(fns[name]) if any(LOAD.match(l) for l in b)]
+    assert len(loops) == (3 if kernel == "chase" else 2), len(loops)
+    for body in loops:
+        loads = [i for i, l in enumerate(body) if LOAD.match(l)]
+        assert len(loads) == 1, body
+        waits = [i for i, l in enumerate(body) if re.match(r"s_waitcnt\s+vmcnt\(0\)", l)]
+        assert waits and waits[0] < loads[0], body
+        assert not any(l.startswith(("global_store", "buffer_store", "flat_store"))
+                       for l in body), body
