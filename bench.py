@@ -110,7 +110,7 @@ def parse():
                          "must repeat the same launches)")
     ap.add_argument("--json-out", default=None,
                     help="file for the full result (default "
-                         "gpurun_out/bench_detail.json); standard output ends "
+                         "results/bench_detail.json); standard output ends "
                          "with a compact headline line")
     ap.add_argument("--record", default=None,
                     help="append one JSON line per timed launch (raw log) to this file")
@@ -607,7 +607,7 @@ def main():
         bat = result["rows"].pop("c5a_cpu_oracle", None)
         if bat and "cpu_baseline" in result:
             result["cpu_baseline"]["batched"] = bat
-    detail = a.json_out or os.path.join("gpurun_out", "bench_detail.json")
+    detail = a.json_out or os.path.join("results", "bench_detail.json")
     report.emit(result, detail, sys.stdout)
     return 0
 

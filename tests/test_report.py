@@ -103,7 +103,7 @@ def full_result():
 def test_headline_line_fits_and_keeps_everything():
     r = full_result()
     assert len(json.dumps(r)) > 8000          # the detail alone would not fit
-    line = report.headline_line(r, "gpurun_out/bench_detail.json")
+    line = report.headline_line(r, "results/bench_detail.json")
     assert len(line.encode()) <= report.LINE_LIMIT
     d = json.loads(line)
     for k in report.REQUIRED:
@@ -128,7 +128,7 @@ def test_headline_line_fits_and_keeps_everything():
     assert d["streaming_gate"]["verdict"] == "latency-bound"
     assert d["f4"] == {b: [20, 4, 24] for b in ("hbm", "infinity_cache", "l2")}
     assert d["f4_fixed_iters"] == {b: [8, 10, 30] for b in ("hbm", "infinity_cache", "l2")}
-    assert d["detail"] == "gpurun_out/bench_detail.json"
+    assert d["detail"] == "results/bench_detail.json"
 
 
 def test_optional_sections_give_way_to_the_limit():
