@@ -131,11 +131,12 @@ def test_residency_is_pinned(c2):
         assert counts[0] == counts[-1] == w // 4
 
 
-@pytest.mark.parametrize("V,K", [(4, 3), (8, 5)])
+@pytest.mark.parametrize("V,K", [(4, 3), (8, 5), (16, 16)])
 def test_vector_indices_past_2_to_32(V, K):
-    """A 20 GiB buffer read in 4- and 8-byte vectors: vector indices exceed
-    2**32 (V = 4) and byte offsets exceed 2**34; the work wraps past the end.
-    Sampled waves, including the last one, are recomputed from the seed."""
+    """A 20 GiB buffer read in 4-, 8- and 16-byte vectors (the last at the
+    largest K): vector indices exceed 2**32 (V = 4) and byte offsets exceed
+    2**34; the work wraps past the end.  Sampled waves, including the last
+    one, are recomputed from the seed."""
     size = 20 * GIB
     seed = sweeps.SEED_BASE + 2
     buf = sweeps.device_buffer(size, seed)
