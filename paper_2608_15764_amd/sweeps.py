@@ -28,7 +28,6 @@ later HBM reads about 6 % slower for a while (under 0.1 s after 1 GiB,
 into whatever is timed next.
 """
 import json
-import math
 import os
 
 import torch

@@ -1,7 +1,6 @@
 """The C ABI used from plain C (gcc, HIP runtime only), checked against the
 oracle."""
 import os
-import shutil
 import subprocess
 
 import pytest

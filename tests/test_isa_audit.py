@@ -5,7 +5,6 @@ vector-memory counter, with no register spills; the LDS-direct loop issues
 loads without a destination register."""
 import os
 import re
-import subprocess
 
 import pytest
 

@@ -1,6 +1,5 @@
 """Counter-audit parser on synthetic rocprofv3 CSVs (no GPU)."""
 import csv
-import os
 
 import pytest
 
