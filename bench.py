@@ -568,6 +568,8 @@ def main():
         lat = sweeps.hbm_latency_ns()
         result["gap"] = sweeps.gap_breakdown(buf, nbytes, L, policy, summ, lat,
                                              waves_list, Ks)
+        # the ceiling the plateau meets: the same read by subsets of the XCDs
+        result["fabric_by_xcd"] = sweeps.fabric_by_xcd(buf, nbytes, policy=policy)
         # one untimed pass of the same sweep under the other cache policies
         pc = {}
         for name, pol in isw.POLICY_NAMES.items():

@@ -475,6 +475,28 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
                 uint32_t* samples, uint32_t n_samples, void* stream,
                 sweep_chase_t* out);
 
+/* Streaming read by a subset of the XCDs (no passage of the paper defines
+ * it; it locates the ceiling the K sweep's plateau meets on MI355X, which
+ * the paper's single-die view leaves open).  The launch has the shape of
+ * the full-grid plain cell, num_cus * waves_per_cu / 4 workgroups of four
+ * waves, pinned like sweep_plain; the dispatcher deals workgroups to the
+ * eight XCDs in turn, and workgroup b works only if bit (b mod 8) of
+ * xcd_mask is set (the others return at once).  The active waves, numbered
+ * densely, run the plain loop with K = 8 loads of 16-byte vectors, adjacent
+ * segments, over groups dealt round robin, reading the first
+ * n_act * groups * 512 vectors of the buffer once, with
+ * groups = floor((bytes / 16) / (n_act * 512)).  Every active wave's record
+ * carries its XCC_ID, so a caller can check the placement.
+ *   xcd_mask      1..255
+ *   waves_per_cu  as sweep_plain (4..32, a multiple of 4)
+ *   opt           cache_policy, stream, pin_occupancy, wave_out (n_act
+ *                 records, with wave_out_cap) are read; the rest is ignored
+ * out: as sweep_plain; waves = n_act active waves, target = issued loads.
+ * Errors: SWEEP_EINVAL (mask, policy, size below one group per active
+ * wave), SWEEP_EALIGN, SWEEP_EOCCUPANCY, SWEEP_EHIP, SWEEP_ENOMEM. */
+int sweep_xcd_subset(const void* buf, size_t bytes, int waves_per_cu, uint32_t xcd_mask,
+                     const sweep_opts_t* opt, sweep_result_t* out);
+
 /* Dependent-chain walkers on several XCDs at once: the latency probe of
  * Section 4.1 resolved by XCD.  The paper's probe ran on one SM, so it
  * could not separate near and far paths; on MI355X every XCD has its own

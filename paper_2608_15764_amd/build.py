@@ -22,8 +22,8 @@ LIB = os.path.join(PKG, "libilpsweep.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels_plain.hip", "kernels_fused.hip", "kernels_lds.hip",
-           "kernels_misc.hip", "kernels_chase.hip", "static_scratch.hip", "runtime.cpp",
-           "plan.cpp"]
+           "kernels_misc.hip", "kernels_chase.hip", "kernels_xcd.hip", "static_scratch.hip",
+           "runtime.cpp", "plan.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

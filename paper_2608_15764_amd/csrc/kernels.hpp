@@ -122,6 +122,20 @@ struct WalkArgs {
   uint64_t* out;           // device [4 * n_walkers]
 };
 
+// Streaming read by the workgroups of chosen XCDs only (sweep_xcd_subset).
+// Workgroup b belongs to XCD b mod 8; the active waves, numbered densely,
+// read groups of kXcdK adjacent 64-lane segments of 16-byte vectors dealt
+// round robin: group i * n_act + w goes to active wave w.
+constexpr int kXcdK = 8;
+struct XcdArgs {
+  const uint8_t* buf;
+  uint64_t groups;         // groups per active wave
+  uint64_t n_act;          // active waves
+  uint32_t mask;           // bit x set: workgroups on XCD x work
+  uint32_t pop;            // set bits in mask
+  sweep_wave_rec_t* rec;   // device [n_act]
+};
+
 // Per-cell result reduced on the device from the wave records.
 struct CellRes {
   uint64_t sum;   // low 32 bits used
@@ -148,6 +162,7 @@ hipError_t static_scratch(int ordinal, uint8_t** ptr);
 const void* plain_kernel(int K, int V, int policy);
 // fused plain batch (kernels_fused.hip)
 const void* fused_kernel(int K, int V, int policy);
+const void* xcd_kernel(int policy);
 // Set `n` records to "empty" (zero sinks, t0 = all ones, t1 = 0), which
 // the finishing kernel's min / max ignore.
 hipError_t launch_clear_records(sweep_wave_rec_t* rec, uint64_t n, hipStream_t st);

@@ -1,0 +1,50 @@
+// Streaming read by a subset of the XCDs: the plain K-load loop (K = 8,
+// 16-byte vectors, adjacent segments, dealt round robin) run only by the
+// workgroups of chosen XCDs, the others returning at once.  It measures the
+// bandwidth one XCD, or a set of them, can draw, which locates the ceiling
+// the sweep's plateau meets.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace ilp {
+
+template <int POL>
+__global__ __launch_bounds__(kPlainWgThreads) void xcd_subset(XcdArgs a) {
+  const uint64_t t0 = wall_ticks();
+  // the dispatcher deals workgroups to the 8 XCDs in turn: b -> XCD b mod 8
+  const uint32_t b = blockIdx.x;
+  const uint32_t x = b & 7u;
+  if (!((a.mask >> x) & 1u)) return;
+  const uint32_t rank = __builtin_popcount(a.mask & ((1u << x) - 1u));
+  const uint32_t awg = (b >> 3) * a.pop + rank;
+  const uint32_t aw = awg * (kPlainWgThreads / kWave) + wave_in_wg();
+  const uint32_t lane = lane_id();
+  uint32_t s = 0, xr = 0;
+  uint64_t p = (uint64_t)aw * (kXcdK * kWave);       // first vector of group aw
+  const uint64_t step = a.n_act * (kXcdK * kWave);
+#pragma unroll 1
+  for (uint64_t i = 0; i < a.groups; ++i) {
+    u32x4 v[kXcdK];
+#pragma unroll
+    for (int j = 0; j < kXcdK; ++j)
+      v[j] = load_seg<16, POL>(a.buf + (p + (uint64_t)j * kWave) * 16u, lane);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < kXcdK; ++j) fold(v[j], s, xr);
+    p += step;
+  }
+  const uint64_t t1 = wall_ticks();
+  wave_epilogue(s, xr, t0, t1, aw, a.rec, nullptr);
+}
+
+const void* xcd_kernel(int policy) {
+  switch (policy) {
+    case SWEEP_CACHE_DEFAULT: return reinterpret_cast<const void*>(&xcd_subset<SWEEP_CACHE_DEFAULT>);
+    case SWEEP_CACHE_NT: return reinterpret_cast<const void*>(&xcd_subset<SWEEP_CACHE_NT>);
+    case SWEEP_CACHE_BYPASS_L1: return reinterpret_cast<const void*>(&xcd_subset<SWEEP_CACHE_BYPASS_L1>);
+    case SWEEP_CACHE_BYPASS_L1_NT: return reinterpret_cast<const void*>(&xcd_subset<SWEEP_CACHE_BYPASS_L1_NT>);
+    default: return nullptr;
+  }
+}
+
+}  // namespace ilp

@@ -164,6 +164,8 @@ _SIG = {
     "sweep_chase": (C.c_int, [_P, C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint32,
                               C.c_int, _P, C.c_uint32, _P,
                               C.POINTER(sweep_chase_t)]),
+    "sweep_xcd_subset": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_uint32,
+                                   C.POINTER(sweep_opts_t), C.POINTER(sweep_result_t)]),
     "sweep_chase_walkers": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint32), C.c_int,
                                       C.c_uint32, C.c_uint32, C.c_int, _P,
                                       C.POINTER(sweep_walker_t)]),
@@ -482,6 +484,16 @@ def sweep_chase(chain, bytes_, start, warm_hops, hops, cache_policy=CACHE_DEFAUL
                            cache_policy, _ptr(samples), n_samples,
                            _stream(stream), C.byref(o)), "sweep_chase")
     return o.as_dict()
+
+
+def sweep_xcd_subset(buf, bytes_, waves_per_cu, xcd_mask, opts=None):
+    """The plain K = 8 read run only by the workgroups of the XCDs in
+    ``xcd_mask`` (bit x: XCD x); returns the result dict of one launch."""
+    r = sweep_result_t()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_xcd_subset(_ptr(buf), bytes_, waves_per_cu, xcd_mask, C.byref(o),
+                                C.byref(r)), "sweep_xcd_subset")
+    return r.as_dict()
 
 
 MAX_WALKERS = 64

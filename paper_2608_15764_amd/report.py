@@ -24,7 +24,7 @@ REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step
 # Optional sections, dropped last-first if the line would exceed the limit.
 OPTIONAL = ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
             "peak_K_at_best", "decline_2_8_at_best", "paper_like", "strict_cg",
-            "gap", "eager", "c5a", "c5b", "streaming_gate", "f4", "f4_fixed_iters",
+            "gap", "fabric", "eager", "c5a", "c5b", "streaming_gate", "f4", "f4_fixed_iters",
             "detail")
 
 
@@ -129,6 +129,11 @@ def compact(result, detail_path=None):
     if isinstance(gap, dict):
         out["gap"] = _pick(gap, ("hbm_latency_ns", "kernel_frac", "ceiling_frac_of_peak",
                                  "tail_loss", "residual_frac", "frac_of_ceiling"), 4)
+    fb = r.get("fabric_by_xcd")
+    if isinstance(fb, dict) and fb:
+        # [min, max] GB/s per class of XCD subset at the lowest occupancy
+        w = min(fb, key=lambda k: int(k))
+        out["fabric"] = fb[w].get("by_class")
     ea = r.get("eager_sweep")
     if isinstance(ea, dict):
         out["eager"] = _pick(ea, ("step_ms", "aggregate_gbps", "dispatch_event_gbps"), 1)

@@ -862,6 +862,51 @@ def latency_ladder(footprints=None, stride=128, hops=8192, n_samples=4096,
     return out
 
 
+FABRIC_MASKS = (("one", tuple(1 << x for x in range(8))),
+                ("group_of_four", (0x0F, 0xF0)),
+                ("two_per_group", (0x55, 0xAA, 0x3C, 0xC3)),
+                ("three_per_group", (0x77, 0xEE, 0xDD, 0xBB)),
+                ("all", (0xFF,)))
+
+
+def fabric_by_xcd(buf, nbytes, waves_list=(4, 8), policy=isw.CACHE_BYPASS_L1_NT, n=5,
+                  masks=FABRIC_MASKS):
+    """Where the plateau's ceiling sits: the plain K = 8 read run only by the
+    workgroups of chosen XCDs (one XCD, a group of four that share a path,
+    two or three from each group, all eight), each mask timed in ``n``
+    launches after a warm-up.  Every active wave's XCC_ID is checked against
+    the XCD its workgroup index names (``misplaced_waves``)."""
+    import numpy as np
+    dt = wave_rec_dtype()
+    n_cus = isw.sweep_device_info()["num_cus"]
+    rec = torch.zeros(n_cus * max(waves_list) * dt.itemsize, dtype=torch.uint8, device="cuda")
+    out = {}
+    for w in waves_list:
+        rows, by_class = {}, {}
+        for cls, ms in masks:
+            for m in ms:
+                opts = isw.make_opts(cache_policy=policy, wave_out=rec)
+                isw.sweep_xcd_subset(buf, nbytes, w, m, opts)           # warm-up
+                runs = [isw.sweep_xcd_subset(buf, nbytes, w, m, opts) for _ in range(n)]
+                r = runs[-1]
+                a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
+                bits = [x for x in range(8) if m >> x & 1]
+                want = np.array([bits[(aw // 4) % len(bits)] for aw in range(r["waves"])])
+                got = a["xcc_id"].astype(np.int64) & 0xF
+                g = _median([x["gbps"] for x in runs])
+                ev = _median([x["issued_bytes"] / (x["event_ms"] * 1e6) for x in runs
+                              if x["event_ms"] > 0])
+                rows[f"{m:#04x}"] = {"class": cls, "xcds": len(bits), "waves": r["waves"],
+                                     "bytes": r["issued_bytes"], "gbps": round(g, 1),
+                                     "event_gbps": round(ev, 1) if ev else None,
+                                     "misplaced_waves": int((got != want).sum())}
+                by_class.setdefault(cls, []).append(g)
+        out[w] = {"masks": rows,
+                  "by_class": {c: [round(min(v), 1), round(max(v), 1)] for c, v in by_class.items()}}
+    del rec
+    return out
+
+
 XCD_FOOTPRINTS = (("l2", 1 * MIB), ("infinity_cache", 64 * MIB), ("hbm", 2 * GIB))
 
 

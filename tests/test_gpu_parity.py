@@ -544,6 +544,51 @@ def test_chase_rejects_bad_arguments():
         assert e.value.code == isw.EINVAL
 
 
+def _xcd_of_active_wave(aw, mask):
+    """The XCD of active wave ``aw``: its workgroup is the (aw // 4)-th
+    active one, counted XCD by XCD in each round of eight workgroups."""
+    bits = [x for x in range(8) if mask >> x & 1]
+    return bits[(aw // 4) % len(bits)]
+
+
+@pytest.mark.parametrize("policy", [1, 3])
+@pytest.mark.parametrize("w", [4, 8])
+@pytest.mark.parametrize("mask", [0x01, 0x80, 0x0F, 0x55, 0x77, 0xFF])
+def test_xcd_subset_matches_oracle(mask, w, policy):
+    """The active waves read the buffer's first issued vectors once: the
+    global sinks equal the oracle's checksum of that prefix; every active
+    wave ran on the XCD its workgroup index names."""
+    nbytes = 64 << 20
+    buf = synth.random_bytes(nbytes, seed=mask * 31 + w, device="cuda")
+    n_cus = isw.sweep_device_info()["num_cus"]
+    n_act = (n_cus * w // 32) * bin(mask).count("1") * 4      # workgroups per XCD x 4 waves
+    ro = recs(n_act)
+    print(f"xcd subset mask {mask:#04x}, {w} waves/CU, policy {policy}", flush=True)
+    r = isw.sweep_xcd_subset(buf, nbytes, w, mask,
+                             isw.make_opts(cache_policy=policy, wave_out=ro))
+    groups = (nbytes // 16) // (n_act * 512)
+    assert r["waves"] == n_act and r["issued_loads"] == n_act * groups * 512
+    words = host_words(buf)
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words[: r["issued_loads"] * 4])
+    rr = decode_recs(ro)
+    got = rr["xcc_id"].astype(np.int64) & 0xF
+    want = np.array([_xcd_of_active_wave(aw, mask) for aw in range(n_act)])
+    assert np.array_equal(got, want)
+    assert r["gbps"] > 0
+
+
+def test_xcd_subset_rejects_bad_arguments():
+    buf = dev_bytes(1 << 20)
+    for args, code in [((buf, 1 << 20, 4, 0), isw.EINVAL),        # empty mask
+                       ((buf, 1 << 20, 4, 256), isw.EINVAL),      # beyond 8 XCDs
+                       ((buf, 1 << 20, 6, 1), isw.EINVAL),        # waves not a multiple of 4
+                       ((buf, 1000, 4, 1), isw.EALIGN),           # not whole segments
+                       ((buf, 1 << 20, 32, 0xFF), isw.EINVAL)]:   # under one group per wave
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_xcd_subset(*args)
+        assert e.value.code == code, args
+
+
 @pytest.mark.parametrize("policy", [0, 2, 3])
 @pytest.mark.parametrize("n_walkers,footprint,warm,hops", [(1, 8192, 10, 300),
                                                           (8, 1 << 20, 100, 500),
@@ -687,6 +732,10 @@ def test_new_bench_rows_run_small():
                                 passes=2)
     gap = sweeps.gap_breakdown(buf, nbytes, nbytes // 16, isw.CACHE_BYPASS_L1_NT, summ, 360.0,
                                waves, Ks)
+    fb = sweeps.fabric_by_xcd(buf, nbytes, waves_list=(4,), n=1,
+                              masks=(("one", (0x01,)), ("all", (0xFF,))))
+    assert set(fb[4]["masks"]) == {"0x01", "0xff"}
+    assert all(m["misplaced_waves"] == 0 and m["gbps"] > 0 for m in fb[4]["masks"].values())
     prod = gap["ceiling_frac_of_peak"] * (1 - gap["tail_loss"]) * gap["residual_frac"]
     assert prod == pytest.approx(gap["kernel_frac"], rel=1e-3)
     assert set(gap["by_waves_per_cu"]) == set(waves)

@@ -136,7 +136,7 @@ def _kernel_names(text):
 
 
 @pytest.mark.parametrize("src", ["kernels_plain", "kernels_fused", "kernels_lds", "kernels_misc",
-                                 "kernels_chase"])
+                                 "kernels_chase", "kernels_xcd"])
 def test_no_kernel_spills_or_uses_scratch(src):
     text = _asm(src)
     names = [n for n in _kernel_names(text) if n.startswith("_Z")]
@@ -241,3 +241,20 @@ def test_chase_loops_keep_one_dependent_load_in_flight(kernel, P):
         assert waits and waits[0] < loads[0], body
         assert not any(l.startswith(("global_store", "buffer_store", "flat_store"))
                        for l in body), body
+
+
+@pytest.mark.parametrize("P", [0, 1, 2, 3])
+def test_xcd_subset_loop_is_the_plain_K8_loop(P):
+    """The XCD-subset read issues the plain loop's eight 16-byte loads per
+    iteration, all before the first wait, and stores nothing in the loop."""
+    text = _asm("kernels_xcd")
+    funcs = _functions(text)
+    name = f"_ZN3ilp10xcd_subsetILi{P}EEEvNS_7XcdArgsE"
+    assert name in funcs, sorted(funcs)
+    body = _loop(funcs[name])
+    assert body is not None
+    loads = [i for i, l in enumerate(body) if LOAD.match(l)]
+    assert len(loads) == 8 and all(re.search(r"dwordx4|b128", body[i]) for i in loads)
+    waits = [i for i, l in enumerate(body) if l.startswith("s_waitcnt") and "vmcnt" in l]
+    assert waits and waits[0] > loads[-1]
+    assert not any(l.startswith(("global_store", "buffer_store", "scratch_")) for l in body)

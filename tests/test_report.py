@@ -63,6 +63,9 @@ def full_result():
         "gap": {"kernel_frac": 0.84, "ceiling_frac_of_peak": 0.98,
                 "frac_of_ceiling": 0.857, "tail_loss": 0.12, "residual_frac": 0.974,
                 "hbm_latency_ns": 360.1, "by_waves_per_cu": {w: {} for w in curves}},
+        "fabric_by_xcd": {8: {"by_class": {"all": [6900.0, 6900.0]}, "masks": {}},
+                          4: {"by_class": {"one": [1340.0, 1350.0], "all": [7000.0, 7000.0]},
+                              "masks": {}}},
         "eager_sweep": {"step_ms": 42.0, "aggregate_gbps": 6442.0,
                         "dispatch_event_gbps": 6678.0},
         "streaming_gate": {"median_gbps": 3900.0, "median_frac": 0.4875,
@@ -125,6 +128,7 @@ def test_headline_line_fits_and_keeps_everything():
     assert d["c5a"]["matches_oracle"] is True
     assert set(d["c5b"]) == {"f32", "bf16", "fp8_e4m3"}
     assert d["gap"]["tail_loss"] == 0.12
+    assert d["fabric"] == {"one": [1340.0, 1350.0], "all": [7000.0, 7000.0]}   # lowest w
     assert d["streaming_gate"]["verdict"] == "latency-bound"
     assert d["f4"] == {b: [20, 4, 24] for b in ("hbm", "infinity_cache", "l2")}
     assert d["f4_fixed_iters"] == {b: [8, 10, 30] for b in ("hbm", "infinity_cache", "l2")}
