@@ -479,14 +479,18 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
  * it; it locates the ceiling the K sweep's plateau meets on MI355X, which
  * the paper's single-die view leaves open).  The launch has the shape of
  * the full-grid plain cell, num_cus * waves_per_cu / 4 workgroups of four
- * waves, pinned like sweep_plain; the dispatcher deals workgroups to the
- * eight XCDs in turn, and workgroup b works only if bit (b mod 8) of
- * xcd_mask is set (the others return at once).  The active waves, numbered
- * densely, run the plain loop with K = 8 loads of 16-byte vectors, adjacent
+ * waves, pinned like sweep_plain.  A workgroup works only if the bit of
+ * its XCD (read from HW_REG_XCC_ID) is set in xcd_mask; the others return
+ * at once.  The dispatcher deals workgroups to the eight XCDs in turn, so
+ * every round of eight workgroups puts one on each XCD, and the active
+ * waves are numbered densely by (round, rank of their XCD in the mask).
+ * Assumes one MI355X partition of eight XCDs.  The active waves run the
+ * plain loop with K = 8 loads of 16-byte vectors, adjacent
  * segments, over groups dealt round robin, reading the first
  * n_act * groups * 512 vectors of the buffer once, with
  * groups = floor((bytes / 16) / (n_act * 512)).  Every active wave's record
- * carries its XCC_ID, so a caller can check the placement.
+ * carries its XCC_ID, so a caller can check that active wave w ran on the
+ * XCD of rank (w / 4) mod popcount(mask) in the mask.
  *   xcd_mask      1..255
  *   waves_per_cu  as sweep_plain (4..32, a multiple of 4)
  *   opt           cache_policy, stream, pin_occupancy, wave_out (n_act
