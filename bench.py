@@ -117,17 +117,6 @@ def parse():
     return ap.parse_args()
 
 
-def _cpu_model():
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return None
-
-
 _WORDS = None
 
 
@@ -187,7 +176,7 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf, num_cus):
     import numpy as np
     import torch
     from oracle import checksums, plan as oplan, splitmix
-    from paper_2608_15764_amd import ilpsweep as isw
+    from paper_2608_15764_amd import environment, ilpsweep as isw
 
     dt = np.dtype([("sum32", "<u4"), ("xor32", "<u4"), ("hw_id", "<u4"),
                    ("xcc_id", "<u4"), ("t0", "<u8"), ("t1", "<u8")])
@@ -224,7 +213,7 @@ def cpu_baseline(buf_seed, nbytes, L, Ks, waves_per_cu, gpu_buf, num_cus):
         "checksum_s": t2 - t1,
         "generate_s": t1 - t0,
         "host_cores_available": os.cpu_count(),
-        "host_cpu": _cpu_model(),
+        "host_cpu": environment.cpu_model(),
         "matches_gpu": ok,
         "multi_process": multi,
     }
