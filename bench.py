@@ -559,6 +559,8 @@ def main():
                                              waves_list, Ks)
         # the ceiling the plateau meets: the same read by subsets of the XCDs
         result["fabric_by_xcd"] = sweeps.fabric_by_xcd(buf, nbytes, policy=policy)
+        # what the equal split costs: shares re-weighted by each XCD's speed
+        result["xcd_weighting"] = sweeps.xcd_weighting(buf, nbytes, policy=policy)
         # one untimed pass of the same sweep under the other cache policies
         pc = {}
         for name, pol in isw.POLICY_NAMES.items():

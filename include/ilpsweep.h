@@ -501,6 +501,24 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
 int sweep_xcd_subset(const void* buf, size_t bytes, int waves_per_cu, uint32_t xcd_mask,
                      const sweep_opts_t* opt, sweep_result_t* out);
 
+/* Static split weighted per XCD (no passage of the paper defines it; the
+ * method gives every wave an equal share, and this measures what unequal
+ * service across XCDs costs that rule).  Same launch shape and loop as
+ * sweep_xcd_subset, but XCD x (read from HW_REG_XCC_ID) owns a contiguous
+ * share of floor(total * weights[x] / sum(weights)) groups, total =
+ * floor((bytes / 16) / 512), dealt round robin over its own grid / 8 * 4
+ * waves; the shares start at group 0 and follow each other in XCD order,
+ * so the read covers the first sum(shares) * 512 vectors once.  XCDs whose
+ * share is 0 return at once.  Active waves are numbered (rank of the XCD
+ * among those with a share) * (waves per XCD) + (wave within the XCD), so
+ * wave_out record i belongs to the XCD of rank i / (waves per XCD).
+ *   weights       host array of 8 finite, non-negative weights, not all 0
+ *   opt           as sweep_xcd_subset
+ * out: as sweep_plain; iters_min / iters_max are the per-wave group counts
+ * over the XCDs with a share.  Errors as sweep_xcd_subset. */
+int sweep_xcd_split(const void* buf, size_t bytes, int waves_per_cu, const double* weights,
+                    const sweep_opts_t* opt, sweep_result_t* out);
+
 /* Dependent-chain walkers on several XCDs at once: the latency probe of
  * Section 4.1 resolved by XCD.  The paper's probe ran on one SM, so it
  * could not separate near and far paths; on MI355X every XCD has its own

@@ -136,6 +136,18 @@ struct XcdArgs {
   sweep_wave_rec_t* rec;   // device [n_act]
 };
 
+// Static split weighted per XCD (sweep_xcd_split): XCD x reads groups
+// [starts[x], starts[x+1]) of kXcdK segments, dealt round robin over its own
+// waves; waves are numbered (rank of the XCD among those with a share,
+// wave within the XCD).
+struct XcdSplitArgs {
+  const uint8_t* buf;
+  uint64_t starts[9];      // group prefix sums per XCD
+  uint32_t per_xcd;        // waves per XCD
+  uint32_t mask;           // XCDs with a nonzero share
+  sweep_wave_rec_t* rec;   // device [popcount(mask) * per_xcd]
+};
+
 // Per-cell result reduced on the device from the wave records.
 struct CellRes {
   uint64_t sum;   // low 32 bits used
@@ -163,6 +175,7 @@ const void* plain_kernel(int K, int V, int policy);
 // fused plain batch (kernels_fused.hip)
 const void* fused_kernel(int K, int V, int policy);
 const void* xcd_kernel(int policy);
+const void* xcd_split_kernel(int policy);
 // Set `n` records to "empty" (zero sinks, t0 = all ones, t1 = 0), which
 // the finishing kernel's min / max ignore.
 hipError_t launch_clear_records(sweep_wave_rec_t* rec, uint64_t n, hipStream_t st);

@@ -413,6 +413,85 @@ int run_prepared(Dev& d, std::vector<Prepared>& ps, hipStream_t st,
   return SWEEP_OK;
 }
 
+// The XCD reads share the launch shape of the full-grid plain cell at
+// K = kXcdK and 16-byte vectors: validated like it (size, occupancy, LDS
+// padding that pins residency), with their own kernel's resources.
+int xcd_prepare(Dev& d, const void* buf, size_t bytes, int waves_per_cu,
+                const sweep_opts_t* opt, const void* fn, Prepared* out) {
+  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(buf) % 16)
+    return fail(SWEEP_EALIGN, "buffer must be 16-byte aligned");
+  PlanIn in;
+  in.bytes = bytes;
+  in.K = kXcdK;
+  in.V = 16;
+  in.kind = SWEEP_KIND_PLAIN;
+  in.waves_per_cu = waves_per_cu;
+  in.L = bytes / 16;
+  in.mode = SWEEP_FIXED_WORK;
+  in.num_cus = d.num_cus;
+  in.lds_per_cu = d.lds_per_cu;
+  in.lds_per_wg_max = d.lds_per_wg_max;
+  in.order = SWEEP_ORDER_ROUND_ROBIN;
+  Prepared p;
+  std::string err;
+  int rc = plan_cell(in, &p.plan, &err);
+  if (rc != SWEEP_OK) return fail(rc, err);
+  p.grid = p.plan.pub.grid_wgs;
+  if (p.grid % 8) return fail(SWEEP_EINVAL, "the grid is not a whole number of workgroups per XCD");
+  p.lds = pin_of(opt) ? p.plan.pub.lds_pad_bytes : 0;
+  p.fn = fn;
+  p.threads = kPlainWgThreads;
+  HIP_TRY(hipFuncGetAttributes(&p.fa, fn));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&p.max_wgs, fn, kPlainWgThreads, p.lds));
+  if ((uint32_t)p.max_wgs < p.plan.wgs_per_cu)
+    return fail(SWEEP_EOCCUPANCY, "kernel resources allow " + std::to_string(p.max_wgs) +
+                                      " workgroups per CU, the launch needs " +
+                                      std::to_string(p.plan.wgs_per_cu));
+  p.c = cell_from(SWEEP_KIND_PLAIN, buf, bytes, kXcdK, 16, waves_per_cu, 0, opt);
+  *out = p;
+  return SWEEP_OK;
+}
+
+// Records what an XCD read issues: `groups` groups of kXcdK segments over
+// n_act active waves, each handling it_min..it_max of them.
+void xcd_account(Prepared* p, uint64_t n_act, uint64_t groups, uint32_t it_min,
+                 uint32_t it_max) {
+  const uint64_t issued = groups * kXcdK * 64;
+  p->c.total_logical_loads = issued;
+  p->plan.pub.waves = (uint32_t)n_act;
+  p->plan.pub.issued_loads = issued;
+  p->plan.pub.issued_bytes = issued * 16;
+  p->plan.pub.mismatch = 0.0;
+  p->plan.pub.iters_min = it_min;
+  p->plan.pub.iters_max = it_max;
+}
+
+// One XCD read: records (the caller's or the library's), the launch with
+// dispatch-stamped events, the finishing kernel, one synchronisation.
+template <class Args>
+int xcd_run(Dev& d, const sweep_opts_t* opt, Prepared& p, uint64_t n_act, Args& a,
+            sweep_result_t* out) {
+  SW_TRY(check_outputs(opt, n_act));
+  sweep_wave_rec_t* wave_out = opt ? opt->wave_out : nullptr;
+  if (!wave_out) SW_TRY(ensure_dev(d.rec, d.rec_cap, n_act));
+  a.rec = wave_out ? wave_out : d.rec;
+  SW_TRY(ensure_dev(d.res, d.res_cap, 1));
+  SW_TRY(ensure_host(d.res_h, d.res_h_cap, 1));
+  SW_TRY(ensure_events(d, 3));
+  hipStream_t st = as_stream(opt);
+  SW_TRY(upload_offsets(d, std::vector<uint64_t>{0, n_act}, st));
+  HIP_TRY(launch_timed(p.fn, p.grid, p.threads, p.lds, st, a, d.ev[0], d.ev[1]));
+  HIP_TRY(launch_finish_cells(a.rec, d.offs, 1, d.res, st));
+  HIP_TRY(hipMemcpyAsync(d.res_h, d.res, sizeof(CellRes), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(d.ev[2], st));
+  HIP_TRY(hipEventSynchronize(d.ev[2]));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
+  fill_result(d, p, d.res_h[0], ms, out);
+  return SWEEP_OK;
+}
+
 int single_cell(const sweep_cell_t& c, const sweep_opts_t* opt, sweep_result_t* out) {
   if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -1167,79 +1246,62 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
 int sweep_xcd_subset(const void* buf, size_t bytes, int waves_per_cu, uint32_t xcd_mask,
                      const sweep_opts_t* opt, sweep_result_t* out) {
   if (!out) return fail(SWEEP_EINVAL, "result pointer is NULL");
-  if (!buf) return fail(SWEEP_EINVAL, "buffer pointer is NULL");
   if (xcd_mask == 0 || xcd_mask > 0xFFu) return fail(SWEEP_EINVAL, "xcd_mask must be 1..255");
-  if (reinterpret_cast<uintptr_t>(buf) % 16)
-    return fail(SWEEP_EALIGN, "buffer must be 16-byte aligned");
-  const int policy = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
-  const void* fn = xcd_kernel(policy);
+  const void* fn = xcd_kernel(opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT);
   if (!fn) return fail(SWEEP_EINVAL, "unknown cache policy");
   std::lock_guard<std::mutex> lk(g_mu);
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
-  // the launch shape of the full-grid plain cell: validates the size and
-  // occupancy and gives the grid and the LDS padding that pins residency
-  PlanIn in;
-  in.bytes = bytes;
-  in.K = kXcdK;
-  in.V = 16;
-  in.kind = SWEEP_KIND_PLAIN;
-  in.waves_per_cu = waves_per_cu;
-  in.L = bytes / 16;
-  in.mode = SWEEP_FIXED_WORK;
-  in.num_cus = d->num_cus;
-  in.lds_per_cu = d->lds_per_cu;
-  in.lds_per_wg_max = d->lds_per_wg_max;
-  in.order = SWEEP_ORDER_ROUND_ROBIN;
-  Plan plan;
-  std::string err;
-  int rc = plan_cell(in, &plan, &err);
-  if (rc != SWEEP_OK) return fail(rc, err);
-  const uint32_t grid = plan.pub.grid_wgs;
-  if (grid % 8) return fail(SWEEP_EINVAL, "the grid is not a whole number of workgroups per XCD");
+  Prepared p;
+  SW_TRY(xcd_prepare(*d, buf, bytes, waves_per_cu, opt, fn, &p));
   const uint32_t pop = (uint32_t)__builtin_popcount(xcd_mask);
-  const uint64_t n_act = (uint64_t)(grid / 8) * pop * (kPlainWgThreads / 64);
+  const uint64_t n_act = (uint64_t)(p.grid / 8) * pop * (kPlainWgThreads / 64);
   const uint64_t groups = (bytes / 16) / (n_act * kXcdK * 64);
   if (groups == 0) return fail(SWEEP_EINVAL, "buffer smaller than one group per active wave");
-  const size_t lds = pin_of(opt) ? plan.pub.lds_pad_bytes : 0;
+  xcd_account(&p, n_act, n_act * groups, (uint32_t)groups, (uint32_t)groups);
+  XcdArgs a{static_cast<const uint8_t*>(buf), groups, n_act, xcd_mask, pop, nullptr};
+  return xcd_run(*d, opt, p, n_act, a, out);
+}
+
+int sweep_xcd_split(const void* buf, size_t bytes, int waves_per_cu, const double* weights,
+                    const sweep_opts_t* opt, sweep_result_t* out) {
+  if (!out || !weights) return fail(SWEEP_EINVAL, "NULL argument");
+  double sum = 0;
+  for (int x = 0; x < 8; ++x) {
+    if (!(weights[x] >= 0.0) || weights[x] > 1e300)
+      return fail(SWEEP_EINVAL, "weights must be finite and non-negative");
+    sum += weights[x];
+  }
+  if (!(sum > 0.0)) return fail(SWEEP_EINVAL, "no XCD has a weight");
+  const void* fn = xcd_split_kernel(opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT);
+  if (!fn) return fail(SWEEP_EINVAL, "unknown cache policy");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Dev* d = nullptr;
+  SW_TRY(current_dev(&d));
   Prepared p;
-  HIP_TRY(hipFuncGetAttributes(&p.fa, fn));
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&p.max_wgs, fn, kPlainWgThreads, lds));
-  if ((uint32_t)p.max_wgs < plan.wgs_per_cu)
-    return fail(SWEEP_EOCCUPANCY, "kernel resources allow " + std::to_string(p.max_wgs) +
-                                      " workgroups per CU, the launch needs " +
-                                      std::to_string(plan.wgs_per_cu));
-  SW_TRY(check_outputs(opt, n_act));
-  const uint64_t issued = n_act * groups * kXcdK * 64;
-  p.c = cell_from(SWEEP_KIND_PLAIN, buf, bytes, kXcdK, 16, waves_per_cu, issued, opt);
-  p.plan = plan;
-  p.plan.pub.waves = (uint32_t)n_act;
-  p.plan.pub.issued_loads = issued;
-  p.plan.pub.issued_bytes = issued * 16;
-  p.plan.pub.mismatch = 0.0;
-  p.plan.pub.iters_min = p.plan.pub.iters_max = (uint32_t)groups;
-  p.fn = fn;
-  p.grid = grid;
-  p.threads = kPlainWgThreads;
-  p.lds = lds;
-  sweep_wave_rec_t* wave_out = opt ? opt->wave_out : nullptr;
-  if (!wave_out) SW_TRY(ensure_dev(d->rec, d->rec_cap, n_act));
-  sweep_wave_rec_t* rec = wave_out ? wave_out : d->rec;
-  SW_TRY(ensure_dev(d->res, d->res_cap, 1));
-  SW_TRY(ensure_host(d->res_h, d->res_h_cap, 1));
-  SW_TRY(ensure_events(*d, 3));
-  hipStream_t st = as_stream(opt);
-  SW_TRY(upload_offsets(*d, std::vector<uint64_t>{0, n_act}, st));
-  const XcdArgs a{static_cast<const uint8_t*>(buf), groups, n_act, xcd_mask, pop, rec};
-  HIP_TRY(launch_timed(fn, grid, kPlainWgThreads, lds, st, a, d->ev[0], d->ev[1]));
-  HIP_TRY(launch_finish_cells(rec, d->offs, 1, d->res, st));
-  HIP_TRY(hipMemcpyAsync(d->res_h, d->res, sizeof(CellRes), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipEventRecord(d->ev[2], st));
-  HIP_TRY(hipEventSynchronize(d->ev[2]));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
-  fill_result(*d, p, d->res_h[0], ms, out);
-  return SWEEP_OK;
+  SW_TRY(xcd_prepare(*d, buf, bytes, waves_per_cu, opt, fn, &p));
+  const uint32_t per_xcd = p.grid / 8 * (kPlainWgThreads / 64);
+  const uint64_t total = (bytes / 16) / (kXcdK * 64);
+  XcdSplitArgs a{};
+  a.buf = static_cast<const uint8_t*>(buf);
+  a.per_xcd = per_xcd;
+  uint64_t acc = 0;
+  uint32_t it_min = ~0u, it_max = 0;
+  for (int x = 0; x < 8; ++x) {
+    a.starts[x] = acc;
+    const uint64_t share = (uint64_t)((double)total * (weights[x] / sum));
+    acc += share;
+    if (share) {
+      a.mask |= 1u << x;
+      it_min = std::min<uint32_t>(it_min, (uint32_t)(share / per_xcd));
+      it_max = std::max<uint32_t>(it_max, (uint32_t)((share + per_xcd - 1) / per_xcd));
+    }
+  }
+  a.starts[8] = acc;
+  if (a.mask == 0) return fail(SWEEP_EINVAL, "every share rounds to zero groups");
+  const uint64_t n_act = (uint64_t)__builtin_popcount(a.mask) * per_xcd;
+  xcd_account(&p, n_act, acc, it_min, it_max);
+  return xcd_run(*d, opt, p, n_act, a, out);
 }
 
 int sweep_chase_walkers(const void* chain, size_t bytes, const uint32_t* starts,

@@ -166,6 +166,8 @@ _SIG = {
                               C.POINTER(sweep_chase_t)]),
     "sweep_xcd_subset": (C.c_int, [_P, C.c_size_t, C.c_int, C.c_uint32,
                                    C.POINTER(sweep_opts_t), C.POINTER(sweep_result_t)]),
+    "sweep_xcd_split": (C.c_int, [_P, C.c_size_t, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(sweep_opts_t), C.POINTER(sweep_result_t)]),
     "sweep_chase_walkers": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint32), C.c_int,
                                       C.c_uint32, C.c_uint32, C.c_int, _P,
                                       C.POINTER(sweep_walker_t)]),
@@ -493,6 +495,19 @@ def sweep_xcd_subset(buf, bytes_, waves_per_cu, xcd_mask, opts=None):
     o = opts if opts is not None else make_opts()
     _check(lib.sweep_xcd_subset(_ptr(buf), bytes_, waves_per_cu, xcd_mask, C.byref(o),
                                 C.byref(r)), "sweep_xcd_subset")
+    return r.as_dict()
+
+
+def sweep_xcd_split(buf, bytes_, waves_per_cu, weights, opts=None):
+    """The same read with a contiguous share of the groups per XCD, in
+    proportion to ``weights`` (8 values, XCD 0 first)."""
+    if len(weights) != 8:
+        raise ValueError("weights takes one value per XCD (8)")
+    w = (C.c_double * 8)(*[float(v) for v in weights])
+    r = sweep_result_t()
+    o = opts if opts is not None else make_opts()
+    _check(lib.sweep_xcd_split(_ptr(buf), bytes_, waves_per_cu, w, C.byref(o), C.byref(r)),
+           "sweep_xcd_split")
     return r.as_dict()
 
 

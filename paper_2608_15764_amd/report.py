@@ -24,7 +24,7 @@ REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step
 # Optional sections, dropped last-first if the line would exceed the limit.
 OPTIONAL = ("curve_peak_gbps", "curve_peak_frac_of_hbm", "best_waves_per_cu",
             "peak_K_at_best", "decline_2_8_at_best", "paper_like", "strict_cg",
-            "gap", "fabric", "eager", "c5a", "c5b", "streaming_gate", "f4", "f4_fixed_iters",
+            "gap", "fabric", "xcd_weighting", "eager", "c5a", "c5b", "streaming_gate", "f4", "f4_fixed_iters",
             "detail")
 
 
@@ -134,6 +134,11 @@ def compact(result, detail_path=None):
         # [min, max] GB/s per class of XCD subset at the lowest occupancy
         w = min(fb, key=lambda k: int(k))
         out["fabric"] = fb[w].get("by_class")
+    xw = r.get("xcd_weighting")
+    if isinstance(xw, dict) and xw:
+        # per occupancy: rate gain of the re-weighted split, even/odd share
+        out["xcd_weighting"] = {w: [v.get("gain"), v.get("even_over_odd_share")]
+                                for w, v in xw.items()}
     ea = r.get("eager_sweep")
     if isinstance(ea, dict):
         out["eager"] = _pick(ea, ("step_ms", "aggregate_gbps", "dispatch_event_gbps"), 1)

@@ -907,6 +907,52 @@ def fabric_by_xcd(buf, nbytes, waves_list=(4, 8), policy=isw.CACHE_BYPASS_L1_NT,
     return out
 
 
+def xcd_weighting(buf, nbytes, waves_list=(4, 8, 16), rounds=4, n=3,
+                  policy=isw.CACHE_BYPASS_L1_NT):
+    """What the method's equal split costs when the XCDs are served unequally:
+    the K = 8 read with a contiguous share of the groups per XCD, starting
+    from equal shares and re-weighted ``rounds`` times by each XCD's measured
+    speed (its share over its finish time, from the per-wave clock records).
+    Per occupancy and round: the shares, each XCD's finish time relative to
+    the mean, and the rate (median of ``n`` launches after a warm-up)."""
+    import numpy as np
+    dt = wave_rec_dtype()
+    n_cus = isw.sweep_device_info()["num_cus"]
+    rec = torch.zeros(n_cus * max(waves_list) * dt.itemsize, dtype=torch.uint8, device="cuda")
+    out = {}
+    for w in waves_list:
+        weights = [1.0] * 8
+        per_xcd = n_cus * w // 8           # waves per XCD
+        rows = []
+        for rnd in range(rounds + 1):
+            opts = isw.make_opts(cache_policy=policy, wave_out=rec)
+            isw.sweep_xcd_split(buf, nbytes, w, weights, opts)          # warm-up
+            gb, fin = [], []
+            for _ in range(n):
+                r = isw.sweep_xcd_split(buf, nbytes, w, weights, opts)
+                a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
+                t0 = int(a["t0"].min())
+                ends = a["t1"].astype(np.int64).reshape(8, per_xcd).max(axis=1) - t0
+                x = (a["xcc_id"].astype(np.int64) & 0xF).reshape(8, per_xcd)
+                if not (x == np.arange(8)[:, None]).all():
+                    raise RuntimeError("a wave ran on another XCD than its share's")
+                gb.append(r["gbps"])
+                fin.append(ends)
+            ends = np.median(np.array(fin), axis=0)
+            total = sum(weights)
+            shares = [v / total for v in weights]
+            rows.append({"round": rnd, "gbps": round(_median(gb), 1),
+                         "shares": [round(v, 4) for v in shares],
+                         "finish_rel": [round(float(e / ends.mean()), 3) for e in ends]})
+            weights = [shares[i] / float(ends[i]) for i in range(8)]
+        even = np.mean([rows[-1]["shares"][i] for i in (0, 2, 4, 6)])
+        odd = np.mean([rows[-1]["shares"][i] for i in (1, 3, 5, 7)])
+        out[w] = {"rounds": rows, "gain": round(rows[-1]["gbps"] / rows[0]["gbps"] - 1, 4),
+                  "even_over_odd_share": round(float(even / odd), 4)}
+    del rec
+    return out
+
+
 XCD_FOOTPRINTS = (("l2", 1 * MIB), ("infinity_cache", 64 * MIB), ("hbm", 2 * GIB))
 
 

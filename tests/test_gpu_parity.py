@@ -577,6 +577,49 @@ def test_xcd_subset_matches_oracle(mask, w, policy):
     assert r["gbps"] > 0
 
 
+@pytest.mark.parametrize("w", [4, 8])
+@pytest.mark.parametrize("weights", [[1, 1, 1, 1, 1, 1, 1, 1],
+                                     [1, 2, 0, 1, 3, 0.5, 1, 1],
+                                     [0, 0, 0, 1, 0, 0, 0, 0],
+                                     [13.5, 11.5, 13.5, 11.5, 13.5, 11.5, 13.5, 11.5]])
+def test_xcd_split_matches_oracle(weights, w):
+    """The weighted split reads each XCD's contiguous share once: the global
+    sinks equal the oracle's checksum of the shares' prefix, and record i
+    comes from the XCD of rank i / (waves per XCD) among those with a share."""
+    nbytes = 64 << 20
+    buf = synth.random_bytes(nbytes, seed=int(sum(weights) * 10) + w, device="cuda")
+    n_cus = isw.sweep_device_info()["num_cus"]
+    per_xcd = n_cus * w // 8          # workgroups per XCD x 4 waves
+    total = (nbytes // 16) // 512
+    tw = float(sum(weights))
+    shares = [int(total * (v / tw)) for v in weights]
+    bits = [x for x in range(8) if shares[x]]
+    ro = recs(len(bits) * per_xcd)
+    print(f"xcd split {weights} at {w} waves/CU", flush=True)
+    r = isw.sweep_xcd_split(buf, nbytes, w, weights,
+                            isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1_NT, wave_out=ro))
+    assert r["waves"] == len(bits) * per_xcd
+    assert r["issued_loads"] == sum(shares) * 512
+    words = host_words(buf)
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words[: r["issued_loads"] * 4])
+    got = decode_recs(ro)["xcc_id"].astype(np.int64) & 0xF
+    want = np.repeat(bits, per_xcd)
+    assert np.array_equal(got, want), (got[::per_xcd].tolist(), bits)
+    per_wave = [shares[x] / per_xcd for x in bits]
+    assert r["iters_min"] == int(min(per_wave)) and r["iters_max"] == -int(-max(per_wave) // 1)
+
+
+def test_xcd_split_rejects_bad_arguments():
+    buf = dev_bytes(1 << 20)
+    for wts in ([0] * 8, [1, -1, 1, 1, 1, 1, 1, 1], [float("nan")] + [1] * 7,
+                [float("inf")] + [1] * 7):
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_xcd_split(buf, 1 << 20, 4, wts)
+        assert e.value.code == isw.EINVAL, wts
+    with pytest.raises(ValueError):
+        isw.sweep_xcd_split(buf, 1 << 20, 4, [1] * 7)
+
+
 def test_xcd_subset_rejects_bad_arguments():
     buf = dev_bytes(1 << 20)
     for args, code in [((buf, 1 << 20, 4, 0), isw.EINVAL),        # empty mask
@@ -732,6 +775,8 @@ def test_new_bench_rows_run_small():
                                 passes=2)
     gap = sweeps.gap_breakdown(buf, nbytes, nbytes // 16, isw.CACHE_BYPASS_L1_NT, summ, 360.0,
                                waves, Ks)
+    xw = sweeps.xcd_weighting(buf, nbytes, waves_list=(4,), rounds=1, n=1)
+    assert len(xw[4]["rounds"]) == 2 and abs(sum(xw[4]["rounds"][1]["shares"]) - 1) < 1e-3
     fb = sweeps.fabric_by_xcd(buf, nbytes, waves_list=(4,), n=1,
                               masks=(("one", (0x01,)), ("all", (0xFF,))))
     assert set(fb[4]["masks"]) == {"0x01", "0xff"}

@@ -244,12 +244,14 @@ def test_chase_loops_keep_one_dependent_load_in_flight(kernel, P):
 
 
 @pytest.mark.parametrize("P", [0, 1, 2, 3])
-def test_xcd_subset_loop_is_the_plain_K8_loop(P):
-    """The XCD-subset read issues the plain loop's eight 16-byte loads per
-    iteration, all before the first wait, and stores nothing in the loop."""
+@pytest.mark.parametrize("kernel", ["xcd_subset", "xcd_split"])
+def test_xcd_subset_loop_is_the_plain_K8_loop(P, kernel):
+    """The XCD reads issue the plain loop's eight 16-byte loads per
+    iteration, all before the first wait, and store nothing in the loop."""
     text = _asm("kernels_xcd")
     funcs = _functions(text)
-    name = f"_ZN3ilp10xcd_subsetILi{P}EEEvNS_7XcdArgsE"
+    args = "XcdArgs" if kernel == "xcd_subset" else "XcdSplitArgs"
+    name = f"_ZN3ilp{len(kernel)}{kernel}ILi{P}EEEvNS_{len(args)}{args}E"
     assert name in funcs, sorted(funcs)
     body = _loop(funcs[name])
     assert body is not None

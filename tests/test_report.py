@@ -66,6 +66,8 @@ def full_result():
         "fabric_by_xcd": {8: {"by_class": {"all": [6900.0, 6900.0]}, "masks": {}},
                           4: {"by_class": {"one": [1340.0, 1350.0], "all": [7000.0, 7000.0]},
                               "masks": {}}},
+        "xcd_weighting": {4: {"gain": 0.001, "even_over_odd_share": 0.98, "rounds": []},
+                          16: {"gain": 0.05, "even_over_odd_share": 1.17, "rounds": []}},
         "eager_sweep": {"step_ms": 42.0, "aggregate_gbps": 6442.0,
                         "dispatch_event_gbps": 6678.0},
         "streaming_gate": {"median_gbps": 3900.0, "median_frac": 0.4875,
@@ -129,6 +131,7 @@ def test_headline_line_fits_and_keeps_everything():
     assert set(d["c5b"]) == {"f32", "bf16", "fp8_e4m3"}
     assert d["gap"]["tail_loss"] == 0.12
     assert d["fabric"] == {"one": [1340.0, 1350.0], "all": [7000.0, 7000.0]}   # lowest w
+    assert d["xcd_weighting"] == {"4": [0.001, 0.98], "16": [0.05, 1.17]}   # JSON keys
     assert d["streaming_gate"]["verdict"] == "latency-bound"
     assert d["f4"] == {b: [20, 4, 24] for b in ("hbm", "infinity_cache", "l2")}
     assert d["f4_fixed_iters"] == {b: [8, 10, 30] for b in ("hbm", "infinity_cache", "l2")}
