@@ -496,8 +496,12 @@ int sweep_chase(const void* chain, size_t bytes, uint32_t start,
  *   opt           cache_policy, stream, pin_occupancy, wave_out (n_act
  *                 records, with wave_out_cap) are read; the rest is ignored
  * out: as sweep_plain; waves = n_act active waves, target = issued loads.
+ * After the launch (outside its timed window) the library checks every
+ * active wave's record: present, and from the XCD its number names.
  * Errors: SWEEP_EINVAL (mask, policy, size below one group per active
- * wave), SWEEP_EALIGN, SWEEP_EOCCUPANCY, SWEEP_EHIP, SWEEP_ENOMEM. */
+ * wave), SWEEP_EALIGN, SWEEP_EOCCUPANCY, SWEEP_EHIP, SWEEP_ENOMEM,
+ * SWEEP_ENODEV (the placement check failed: workgroups were not dealt one
+ * per XCD in each round of eight, so the read is not the one described). */
 int sweep_xcd_subset(const void* buf, size_t bytes, int waves_per_cu, uint32_t xcd_mask,
                      const sweep_opts_t* opt, sweep_result_t* out);
 

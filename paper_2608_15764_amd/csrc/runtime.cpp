@@ -467,11 +467,15 @@ void xcd_account(Prepared* p, uint64_t n_act, uint64_t groups, uint32_t it_min,
   p->plan.pub.iters_max = it_max;
 }
 
-// One XCD read: records (the caller's or the library's), the launch with
-// dispatch-stamped events, the finishing kernel, one synchronisation.
+// One XCD read: records (the caller's or the library's, cleared first),
+// the launch with dispatch-stamped events, the finishing kernel, one
+// synchronisation, then a check that active wave i wrote its record from
+// XCD want[i]: if the dispatcher did not put one workgroup of each round of
+// eight on every XCD, the dense numbering does not hold, groups were read
+// twice or not at all, and the call fails instead of reporting a rate.
 template <class Args>
 int xcd_run(Dev& d, const sweep_opts_t* opt, Prepared& p, uint64_t n_act, Args& a,
-            sweep_result_t* out) {
+            const std::vector<uint8_t>& want, sweep_result_t* out) {
   SW_TRY(check_outputs(opt, n_act));
   sweep_wave_rec_t* wave_out = opt ? opt->wave_out : nullptr;
   if (!wave_out) SW_TRY(ensure_dev(d.rec, d.rec_cap, n_act));
@@ -481,11 +485,21 @@ int xcd_run(Dev& d, const sweep_opts_t* opt, Prepared& p, uint64_t n_act, Args& 
   SW_TRY(ensure_events(d, 3));
   hipStream_t st = as_stream(opt);
   SW_TRY(upload_offsets(d, std::vector<uint64_t>{0, n_act}, st));
+  HIP_TRY(launch_clear_records(a.rec, n_act, st));
   HIP_TRY(launch_timed(p.fn, p.grid, p.threads, p.lds, st, a, d.ev[0], d.ev[1]));
   HIP_TRY(launch_finish_cells(a.rec, d.offs, 1, d.res, st));
   HIP_TRY(hipMemcpyAsync(d.res_h, d.res, sizeof(CellRes), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(d.ev[2], st));
   HIP_TRY(hipEventSynchronize(d.ev[2]));
+  std::vector<sweep_wave_rec_t> h(n_act);
+  HIP_TRY(hipMemcpy(h.data(), a.rec, n_act * sizeof(sweep_wave_rec_t), hipMemcpyDeviceToHost));
+  for (uint64_t i = 0; i < n_act; ++i)
+    if (h[i].t0 == 0 || (h[i].xcc_id & 0xFu) != want[i])
+      return fail(SWEEP_ENODEV, "active wave " + std::to_string(i) +
+                                    (h[i].t0 == 0 ? " wrote no record"
+                                                  : " ran on XCD " + std::to_string(h[i].xcc_id & 0xFu) +
+                                                        ", not " + std::to_string(want[i])) +
+                                    ": workgroups were not dealt one per XCD per round of eight");
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
   fill_result(d, p, d.res_h[0], ms, out);
@@ -1260,7 +1274,13 @@ int sweep_xcd_subset(const void* buf, size_t bytes, int waves_per_cu, uint32_t x
   if (groups == 0) return fail(SWEEP_EINVAL, "buffer smaller than one group per active wave");
   xcd_account(&p, n_act, n_act * groups, (uint32_t)groups, (uint32_t)groups);
   XcdArgs a{static_cast<const uint8_t*>(buf), groups, n_act, xcd_mask, pop, nullptr};
-  return xcd_run(*d, opt, p, n_act, a, out);
+  // active wave w belongs to workgroup w / 4, the (w / 4) mod pop-th active
+  // XCD of its round
+  std::vector<uint8_t> bits, want(n_act);
+  for (uint8_t x = 0; x < 8; ++x)
+    if ((xcd_mask >> x) & 1u) bits.push_back(x);
+  for (uint64_t w = 0; w < n_act; ++w) want[w] = bits[(w / 4) % pop];
+  return xcd_run(*d, opt, p, n_act, a, want, out);
 }
 
 int sweep_xcd_split(const void* buf, size_t bytes, int waves_per_cu, const double* weights,
@@ -1301,7 +1321,11 @@ int sweep_xcd_split(const void* buf, size_t bytes, int waves_per_cu, const doubl
   if (a.mask == 0) return fail(SWEEP_EINVAL, "every share rounds to zero groups");
   const uint64_t n_act = (uint64_t)__builtin_popcount(a.mask) * per_xcd;
   xcd_account(&p, n_act, acc, it_min, it_max);
-  return xcd_run(*d, opt, p, n_act, a, out);
+  std::vector<uint8_t> bits, want(n_act);
+  for (uint8_t x = 0; x < 8; ++x)
+    if ((a.mask >> x) & 1u) bits.push_back(x);
+  for (uint64_t w = 0; w < n_act; ++w) want[w] = bits[w / per_xcd];
+  return xcd_run(*d, opt, p, n_act, a, want, out);
 }
 
 int sweep_chase_walkers(const void* chain, size_t bytes, const uint32_t* starts,
