@@ -1,7 +1,7 @@
 """SplitMix64 buffer generator (oracle side).
 
-The paper fills its device buffers synthetically but does not say how.  This
-build fixes the fill to a counter-based generator so that any word of any
+The paper fills its device buffers synthetically but does not say how.  The
+library fixes the fill to a counter-based generator so that any word of any
 buffer can be recomputed independently on the CPU:
 
     word(i) = low 32 bits of SplitMix64 output number i (0-based),

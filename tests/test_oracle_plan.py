@@ -80,7 +80,7 @@ def test_wave_group_meets_the_paper_bound_for_K_1_to_16():
 
 
 def test_per_thread_floor_cannot_meet_the_bound_at_2_26():
-    # why the build does not use the paper's per-thread floor for K=1..16
+    # why the library does not use the paper's per-thread floor for K=1..16
     L = 2**26
     for w in (1, 4, 8):
         T = 256 * 4 * w * 64
