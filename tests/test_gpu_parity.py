@@ -199,6 +199,49 @@ def test_lds_paths_match_oracle(kind, D, W, grid, n_vec, L, policy):
     assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
 
 
+def _random_lds_cases(n=32, seed=20261204):
+    """Seeded random LDS-path cells: path, depth, waves per workgroup (ring
+    within 64 KiB), grid, allocation, ragged target and cache policy."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        W = int(rng.choice([1, 2, 4, 8, 16]))
+        D = int(rng.integers(1, 17))
+        if W * D > 64:
+            continue
+        grid = int(rng.integers(1, 7))
+        n_vec = 64 * int(rng.integers(1, 151))
+        Q = int(rng.integers(1, 201))
+        L = 64 * D * Q + int(rng.integers(0, 64 * D))
+        out.append((int(rng.integers(1, 3)), D, W, grid, n_vec, L, int(rng.integers(0, 4))))
+    return out
+
+
+@pytest.mark.parametrize("kind,D,W,grid,n_vec,L,policy", _random_lds_cases())
+def test_lds_paths_random_cells_match_oracle(kind, D, W, grid, n_vec, L, policy):
+    """Per lane, per wave and global sinks of both LDS paths against the
+    oracle on seeded random cells (most of them wrap the allocation)."""
+    nbytes = n_vec * 16
+    buf = synth.random_bytes(nbytes, seed=n_vec + 3 * D + W, device="cuda")
+    n_waves = grid * W
+    lo = lanes(n_waves * 64)
+    ro = recs(n_waves)
+    opts = isw.make_opts(grid_wgs=grid, cache_policy=policy, lane_out=lo, wave_out=ro)
+    fn = isw.sweep_lds_async if kind == 1 else isw.sweep_lds_matched_plain
+    r = fn(buf, nbytes, D, 16, W, L, opts)
+    p = oplan.wave_group(L, D, n_waves)
+    assert r["issued_loads"] == p["issued"]
+    assert (r["iters_min"], r["iters_max"]) == (p["iters_min"], p["iters_max"])
+    words = host_words(buf)
+    ws, wx = checksums.per_lane(words, 16, D, p["Q"], n_waves)
+    gs, gx = decode_lanes(lo, n_waves)
+    assert np.array_equal(gs, ws) and np.array_equal(gx, wx)
+    rr = decode_recs(ro)
+    os_, ox = checksums.per_wave(words, 16, D, p["Q"], n_waves)
+    assert np.array_equal(rr["sum32"], os_) and np.array_equal(rr["xor32"], ox)
+    assert (r["sum32"], r["xor32"]) == checksums.combine(ws, wx)
+
+
 @pytest.mark.parametrize("kind_b", ["lds_async", "plain"])
 @pytest.mark.parametrize("D,wa,wb", [(4, 4, 4), (8, 4, 4), (3, 1, 3),
                                      (5, 2, 0), (2, 0, 2), (16, 8, 8)])
