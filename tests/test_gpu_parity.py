@@ -962,6 +962,50 @@ def test_fused_batch_graph_matches_the_oracle(K, w, pol):
                 assert r["window_ns"] > 0
 
 
+@pytest.mark.parametrize("case", range(8))
+def test_fused_batch_random_points_match_the_oracle(case):
+    """Seeded random batches run as one fused launch: 3-12 points of one
+    configuration (K, width, occupancy, policy drawn per case) at random
+    offsets and sizes in one buffer, with ragged targets that may wrap the
+    point's region several times; every point equals the oracle on every
+    replay."""
+    rng = np.random.default_rng(1000 + case)
+    nbytes = 32 << 20
+    seed = SEED + 70 + case
+    buf = dev_bytes(nbytes)
+    isw.sweep_fill_u32(buf, nbytes, seed)
+    words = splitmix.buffer_words(seed, nbytes)
+    K = int(rng.integers(1, 17))
+    V = int(rng.choice([4, 8, 16]))
+    w = int(rng.choice([4, 8, 12, 16, 20, 24, 28]))
+    pol = int(rng.integers(0, 4))
+    seg = 64 * V
+    pts = []
+    for _ in range(int(rng.integers(3, 13))):
+        size = seg * int(rng.integers(1, (4 << 20) // seg + 1))
+        off = seg * int(rng.integers(0, (nbytes - size) // seg + 1))
+        L = int(rng.integers(64 * K, 3 * size // V + 64 * K + 1))
+        pts.append((off, size, L))
+    cells = [isw.make_cell(buf.data_ptr() + o, b, K, V, w, L, cache_policy=pol)
+             for o, b, L in pts]
+    print(f"random fused batch {case}: K={K} V={V} w={w} policy={pol}, {len(pts)} points",
+          flush=True)
+    try:
+        g = isw.sweep_graph_create(cells, isw.make_opts(fuse=True))
+    except isw.SweepError as e:
+        assert e.code == isw.EOCCUPANCY
+        pytest.skip("configuration cannot reach its occupancy")
+    with g:
+        for rep in range(2):
+            res, _ = isw.sweep_graph_launch(g)
+            for (o, b, L), r in zip(pts, res):
+                p = oplan.wave_group(L, K, r["waves"])
+                want = checksums.combine(*checksums.per_wave(
+                    words, V, K, p["Q"], r["waves"], base=o // V, n_vec=b // V))
+                assert (r["sum32"], r["xor32"]) == want, (rep, o, b, L)
+                assert r["issued_loads"] == p["issued"]
+
+
 def test_fused_batch_groups_runs_of_equal_cells():
     """Only consecutive cells with the same kernel and launch shape fuse; a
     cell of another kind, order or configuration between them splits the
