@@ -208,3 +208,64 @@ def emit(result, detail_path, out):
     out.write(line + "\n")
     out.flush()
     return line
+
+
+def summarize(result):
+    """A short plain-text reading of a full result (the detail file): the
+    headline, the roofline, where the gap goes, and one line per extra
+    configuration that the run holds."""
+    c = compact(result)
+    rl = c.get("roofline") or {}
+    lines = [f"{c.get('metric')}: {c.get('value')} {c.get('unit')} "
+             f"({c.get('steps')} steps, {c.get('ms_per_step')} ms per step)"]
+    if rl:
+        tr = rl.get("traffic")
+        ab = rl.get("algorithmic_bytes_per_launch")
+        ratio = f", HBM traffic {tr / ab:.5f}x algorithmic" if tr and ab else ""
+        lines.append(f"roofline: {rl.get('achieved')} of {rl.get('peak')} {rl.get('unit')} "
+                     f"({100 * rl.get('frac', 0):.1f} %, {rl.get('bound')}-bound){ratio}")
+    if "curve_peak_gbps" in c:
+        lines.append(f"best cell: {c['curve_peak_gbps']} GB/s at {c.get('best_waves_per_cu')} "
+                     f"waves/CU, K = {c.get('peak_K_at_best')}")
+    pl = c.get("paper_like")
+    if pl:
+        lines.append(f"paper-like cell ({pl.get('waves_per_cu')} waves/CU): K = 2->8 change "
+                     f"{100 * pl.get('decline_2_8', 0):+.2f} %")
+    g = c.get("gap")
+    if g:
+        lines.append(f"gap: design ceiling {g.get('ceiling_frac_of_peak')} x (1 - tail "
+                     f"{g.get('tail_loss')}) x residual {g.get('residual_frac')} = kernel "
+                     f"{g.get('kernel_frac')}")
+    if c.get("fabric"):
+        lines.append("fabric by XCD subset (GB/s, min-max): " + ", ".join(
+            f"{k} {v[0]}-{v[1]}" for k, v in c["fabric"].items()))
+    if c.get("c5a"):
+        a = c["c5a"]
+        lines.append(f"batched sweep: {a.get('batched_aggregate_gbps')} GB/s "
+                     f"({a.get('chosen_plan')}, oracle match {a.get('matches_oracle')})")
+    if c.get("c5b"):
+        lines.append("precision sums: " + ", ".join(
+            f"{k} {v.get('gbps')} GB/s (within bound {v.get('within_bound')})"
+            for k, v in c["c5b"].items()))
+    cb = c.get("cpu_baseline")
+    if cb:
+        lines.append(f"CPU oracle: {cb.get('value')} {cb.get('unit')} on {cb.get('cores')} "
+                     f"core(s), matches GPU {cb.get('matches_gpu')}")
+    errs = [k for k in result if k.endswith("_error")]
+    for k in errs:
+        lines.append(f"{k}: {result[k]}")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="Summarize a bench detail file")
+    ap.add_argument("detail", nargs="?", default=os.path.join("results", "bench_detail.json"))
+    a = ap.parse_args(argv)
+    with open(a.detail) as f:
+        print(summarize(json.load(f)))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

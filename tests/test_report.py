@@ -171,3 +171,15 @@ def test_missing_sections_are_tolerated():
         del r[k]
     d = json.loads(report.headline_line(r))
     assert d["cpu_baseline"] is None and "c5a" not in d and "detail" not in d
+
+
+def test_summarize_reads_a_full_result(tmp_path):
+    r = full_result()
+    r["fabric_by_xcd_error"] = "sweep_xcd_subset: no usable gfx950 device (-6): ..."
+    text = report.summarize(r)
+    assert text.splitlines()[0].startswith(r["metric"])
+    assert "roofline:" in text and "gap:" in text and "batched sweep:" in text
+    assert "fabric by XCD subset" in text and "fabric_by_xcd_error" in text
+    p = tmp_path / "d.json"
+    report.write_detail(r, str(p))
+    assert report.main([str(p)]) == 0
