@@ -417,3 +417,36 @@ def test_chase_full_size():
     finally:
         del chain
         torch.cuda.empty_cache()
+
+
+def test_walkers_full_size():
+    """The per-XCD latency row's walkers at a cold footprint: 64 walkers
+    spread along a 256 MiB chain, each landing where the oracle's walk from
+    its start lands; one XCD per workgroup in turn."""
+    from oracle import chase
+    footprint = 256 << 20
+    chain, starts = synth.chase_chain_starts(footprint, 128, sweeps.SEED_BASE + 9, 64,
+                                             device="cuda")
+    words = chain.view(torch.int32).cpu().numpy()
+    try:
+        out = isw.sweep_chase_walkers(chain, footprint, starts, 0, 2000, isw.CACHE_BYPASS_L1)
+        for s0, r in zip(starts, out):
+            assert r["final_index"] == chase.follow(words, s0, 2000)
+            assert 50 < r["ns_per_hop"] < 5000
+        assert len({r["xcc_id"] for r in out}) == 8
+    finally:
+        del chain
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mask", [0x01, 0x0F, 0x77, 0xFF])
+def test_xcd_subset_full_size(c2, mask):
+    """The fabric row's read on the bench's 1 GiB buffer: the global sinks
+    equal the oracle's checksum of the issued prefix, for one XCD, a group,
+    three per group and all eight."""
+    buf, nbytes, seed, _whole = c2
+    r = isw.sweep_xcd_subset(buf, nbytes, 4, mask,
+                             isw.make_opts(cache_policy=isw.CACHE_BYPASS_L1_NT))
+    words = splitmix.words(seed, 0, r["issued_loads"] * 4)
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words)
+    assert r["gbps"] > 0
