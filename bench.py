@@ -94,7 +94,7 @@ def parse():
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
                     choices=["c3", "c4", "c5a", "c5b", "c3counters", "c2counters",
-                             "c4counters", "c4stalls", "f3counters", "next"],
+                             "c4counters", "c4stalls", "f3counters", "f3ksweep", "next"],
                     help="run only one extra configuration (no K sweep); "
                          "the *counters modes and c4stalls run cells one launch "
                          "per call for a separate rocprofv3 counter run")
@@ -435,6 +435,18 @@ def main():
         return 0
     if a.only == "f3counters":
         man = sweeps.order_counter_pass(policy=policy, manifest=a.manifest)
+        print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only == "f3ksweep":
+        # every K from 1 to 16 over the 128 MiB allocation, at 2 and 4
+        # waves/SIMD: where the wrapped volume realigns with the allocation
+        man = []
+        for w in (8, 16):
+            man += sweeps.order_counter_pass(sizes=(128 << 20,), waves_per_cu=w,
+                                             Ks=range(1, 17), policy=policy)
+        if a.manifest:
+            with open(a.manifest, "w") as f:
+                json.dump(man, f)
         print(json.dumps({"only": a.only, "launches": len(man)}))
         return 0
     if a.only == "c2counters":
