@@ -734,8 +734,12 @@ def run_extras(a, isw, sweeps, only=None, best_w=None):
     if only in (None, "next"):
         t = time.perf_counter()
         MIB = 1 << 20
+        # K = 3 and 6 beside the powers of two: around the caches the
+        # wrapped volume lands concurrent loads on shared segments only at
+        # some K, and the unaligned ones show the loads' own response
         rows["f2_f3_order_footprint"] = sweeps.order_footprint(
-            [2 * MIB, 4 * MIB, 8 * MIB, 16 * MIB, 128 * MIB, GIB, 4 * GIB])
+            [2 * MIB, 4 * MIB, 8 * MIB, 16 * MIB, 128 * MIB, GIB, 4 * GIB],
+            Ks=(1, 2, 3, 4, 6, 8))
         rows["f2_f3_order_footprint"]["wall_s"] = time.perf_counter() - t
         t = time.perf_counter()
         rows["f4_regime_map"] = sweeps.regime_map()
