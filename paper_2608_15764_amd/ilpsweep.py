@@ -264,20 +264,24 @@ def make_opts(stream=None, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
 
 # ------------------------------------------------------------ entry points
 def sweep_init(ordinal=0):
+    """Initialise the library on HIP device ``ordinal`` (makes it current)."""
     _check(lib.sweep_init(ordinal), "sweep_init")
 
 
 def sweep_shutdown():
+    """Free the library's device memory and events on every device."""
     _check(lib.sweep_shutdown(), "sweep_shutdown")
 
 
 def sweep_device_info():
+    """Properties of the current device as a dict (CUs, LDS, caches, clocks)."""
     d = sweep_device_t()
     _check(lib.sweep_device_info(C.byref(d)), "sweep_device_info")
     return d.as_dict()
 
 
 def sweep_calibrate_clock(seconds=0.2):
+    """Measure the device wall clock against the host over about ``seconds``; returns Hz."""
     hz = C.c_double()
     _check(lib.sweep_calibrate_clock(seconds, C.byref(hz)), "sweep_calibrate_clock")
     return hz.value
@@ -286,6 +290,7 @@ def sweep_calibrate_clock(seconds=0.2):
 def sweep_plan(bytes_, K, vec_width, waves_per_cu, total_logical_loads,
                mode=FIXED_WORK, fixed_iters=0, num_cus=256, grid_wgs=0,
                order=ORDER_ROUND_ROBIN):
+    """Host-only fixed-work plan of a cell (no GPU needed); returns a dict."""
     p = sweep_plan_t()
     _check(lib.sweep_plan(bytes_, K, vec_width, waves_per_cu,
                           total_logical_loads, mode, fixed_iters, num_cus,
@@ -294,6 +299,7 @@ def sweep_plan(bytes_, K, vec_width, waves_per_cu, total_logical_loads,
 
 
 def sweep_fill_u32(buf, bytes_, seed, stream=None):
+    """Fill ``bytes_`` of ``buf`` with the seeded SplitMix64 words (untimed setup)."""
     _check(lib.sweep_fill_u32(_ptr(buf), bytes_, seed & (2**64 - 1),
                               _stream(stream)), "sweep_fill_u32")
 
@@ -308,24 +314,28 @@ def _cell_call(fn, name, buf, bytes_, K, vec_width, waves_per_cu, L, opts):
 
 def sweep_plain(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
                 opts=None):
+    """One plain K-load cell; returns the result dict (sinks, issued loads, window, GB/s)."""
     return _cell_call(lib.sweep_plain, "sweep_plain", buf, bytes_, K,
                       vec_width, waves_per_cu, total_logical_loads, opts)
 
 
 def sweep_plain_noalloc(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
                         opts=None):
+    """``sweep_plain`` with no allocation: its scratch is a static device array."""
     return _cell_call(lib.sweep_plain_noalloc, "sweep_plain_noalloc", buf, bytes_, K,
                       vec_width, waves_per_cu, total_logical_loads, opts)
 
 
 def sweep_lds_async(buf, bytes_, depth, vec_width, waves_per_cu,
                     total_logical_loads, opts=None):
+    """One LDS-direct ring cell of depth ``depth`` (16-byte requests)."""
     return _cell_call(lib.sweep_lds_async, "sweep_lds_async", buf, bytes_,
                       depth, vec_width, waves_per_cu, total_logical_loads, opts)
 
 
 def sweep_lds_matched_plain(buf, bytes_, depth, vec_width, waves_per_cu,
                             total_logical_loads, opts=None):
+    """The matched register ring of ``sweep_lds_async`` (load, LDS write, LDS read)."""
     return _cell_call(lib.sweep_lds_matched_plain, "sweep_lds_matched_plain",
                       buf, bytes_, depth, vec_width, waves_per_cu,
                       total_logical_loads, opts)
@@ -333,6 +343,7 @@ def sweep_lds_matched_plain(buf, bytes_, depth, vec_width, waves_per_cu,
 
 def sweep_two_stream(buf, bytes_, depth, waves_plain, waves_async,
                      total_logical_loads, opts=None):
+    """Two co-resident streams in one workgroup, plain and LDS-direct; two result dicts."""
     r = (sweep_result_t * 2)()
     o = opts if opts is not None else make_opts()
     _check(lib.sweep_two_stream(_ptr(buf), bytes_, depth, waves_plain,
@@ -343,6 +354,7 @@ def sweep_two_stream(buf, bytes_, depth, waves_plain, waves_async,
 
 def sweep_two_stream_kind(buf, bytes_, depth, waves_a, waves_b, kind_b,
                           total_logical_loads, opts=None):
+    """Two co-resident streams in one workgroup, stream B of ``kind_b``; two result dicts."""
     r = (sweep_result_t * 2)()
     o = opts if opts is not None else make_opts()
     _check(lib.sweep_two_stream_kind(_ptr(buf), bytes_, depth, waves_a, waves_b,
@@ -353,6 +365,7 @@ def sweep_two_stream_kind(buf, bytes_, depth, waves_a, waves_b, kind_b,
 
 def sweep_two_stream_split(buf, bytes_, depth, waves_a, waves_b, kind_b,
                            total_logical_loads, opts=None):
+    """The two streams on different CUs; two result dicts."""
     r = (sweep_result_t * 2)()
     o = opts if opts is not None else make_opts()
     _check(lib.sweep_two_stream_split(_ptr(buf), bytes_, depth, waves_a, waves_b,
@@ -364,6 +377,7 @@ def sweep_two_stream_split(buf, bytes_, depth, waves_a, waves_b, kind_b,
 def make_cell(buf, bytes_, K, vec_width, waves_per_cu, total_logical_loads,
               kind=KIND_PLAIN, cache_policy=CACHE_DEFAULT, mode=FIXED_WORK,
               fixed_iters=0, grid_wgs=0, order=ORDER_ROUND_ROBIN):
+    """A ``sweep_cell_t`` for the sweep driver, graphs and the batched sweep."""
     c = sweep_cell_t()
     c.kind = kind
     c.K = K
@@ -406,6 +420,7 @@ def sweep_run(cells, opts=None, raw=False):
 
 
 def sweep_batched(cells, opts=None, raw=False):
+    """Capture ``cells`` into a hipGraph, launch it once, destroy it; (results, graph ms)."""
     arr = cell_array(cells)
     res = (sweep_result_t * len(arr))()
     o = opts if opts is not None else make_opts()
@@ -432,6 +447,7 @@ class SweepGraph:
 
 
 def sweep_graph_create(cells, opts=None):
+    """Capture ``cells`` once into a replayable graph (a context manager)."""
     arr = cell_array(cells)
     h = _P()
     o = opts if opts is not None else make_opts()
@@ -441,6 +457,7 @@ def sweep_graph_create(cells, opts=None):
 
 
 def sweep_graph_launch(graph, stream=None, raw=False):
+    """Replay a captured graph; (results, graph ms), or raw ctypes results."""
     res = (sweep_result_t * graph.n)()
     ms = C.c_double()
     _check(lib.sweep_graph_launch(graph.handle, _stream(stream), res,
@@ -449,6 +466,7 @@ def sweep_graph_launch(graph, stream=None, raw=False):
 
 
 def sweep_graph_destroy(graph):
+    """Free a captured graph and its scratch."""
     if graph is not None and graph.handle:
         _check(lib.sweep_graph_destroy(graph.handle), "sweep_graph_destroy")
         graph.handle = None
@@ -456,6 +474,7 @@ def sweep_graph_destroy(graph):
 
 def sweep_autotune(buf, bytes_, vec_widths, Ks, waves_per_cu,
                    cache_policy=CACHE_DEFAULT, reps=3):
+    """Time every (width, K, waves) candidate of a plain cell; the best and its GB/s."""
     vw = (C.c_int * len(vec_widths))(*vec_widths)
     ks = (C.c_int * len(Ks))(*Ks)
     ws = (C.c_int * len(waves_per_cu))(*waves_per_cu)
@@ -470,6 +489,7 @@ def sweep_autotune(buf, bytes_, vec_widths, Ks, waves_per_cu,
 
 
 def sweep_reduce_fp(payload, n_elems, dtype, waves_per_cu=32, opts=None):
+    """The compensated streaming sum of an FP32/BF16/FP8 payload; (FP64 sum, result dict)."""
     s = C.c_double()
     r = sweep_result_t()
     o = opts if opts is not None else make_opts()
@@ -481,6 +501,7 @@ def sweep_reduce_fp(payload, n_elems, dtype, waves_per_cu=32, opts=None):
 
 def sweep_chase(chain, bytes_, start, warm_hops, hops, cache_policy=CACHE_DEFAULT,
                 samples=None, n_samples=0, stream=None):
+    """The dependent pointer chase of one lane; a result dict (final index, ns per hop)."""
     o = sweep_chase_t()
     _check(lib.sweep_chase(_ptr(chain), bytes_, start, warm_hops, hops,
                            cache_policy, _ptr(samples), n_samples,
@@ -528,12 +549,15 @@ def sweep_chase_walkers(chain, bytes_, starts, warm_hops, hops, cache_policy=CAC
 
 
 def sweep_strerror(code):
+    """Text of an error code."""
     return lib.sweep_strerror(code).decode()
 
 
 def sweep_last_error():
+    """Text of the calling thread's last error."""
     return lib.sweep_last_error().decode()
 
 
 def sweep_version():
+    """Library version string."""
     return lib.sweep_version().decode()
