@@ -267,6 +267,9 @@ def main(argv=None):
     c3.add_argument("--counters", nargs="+", required=True,
                     help="counter_collection CSVs (or directories), one per pass")
     c3.add_argument("--fetch-scale", type=float, default=None)
+    c3.add_argument("--calib-bytes", type=int, default=None,
+                    help="size of the device copies in the FETCH_SIZE pass: the "
+                         "fetch scale is read from them (instead of --fetch-scale)")
     c3.add_argument("--kernel", default="plain_kload",
                     help="substring naming the manifest's kernels")
     c3.add_argument("--cus", type=int, default=None)
@@ -278,10 +281,19 @@ def main(argv=None):
         import json
         with open(a.manifest) as f:
             man = json.load(f)
-        tab = cell_table([counter_rows(p) for p in a.counters], man, a.fetch_scale,
-                         a.kernel, a.cus, a.xccs)
+        runs = [counter_rows(p) for p in a.counters]
+        scale = a.fetch_scale
+        if scale is None and a.calib_bytes:
+            scales = [calib_scale(r, "FETCH_SIZE", a.calib_bytes) for r in runs]
+            scales = [x for x in scales if x is not None]
+            if not scales:
+                raise SystemExit("--calib-bytes: no device copy with FETCH_SIZE in any pass")
+            scale = scales[0]
+        tab = cell_table(runs, man, scale, a.kernel, a.cus, a.xccs)
         lines = ["# rocprofv3 per-cell counters (generated by paper_2608_15764_amd.rocprof)"]
         lines += [f"# command: {c}" for c in a.command]
+        if scale:
+            lines.append(f"# FETCH_SIZE scale (device copies of known size): {scale:.6g}")
         keys = [k for k in CELL_KEYS if man and k in man[0]]
         lines.append(f"# {' '.join(keys)}: counter medians over non-warm-up launches")
         for key, row in tab.items():

@@ -170,3 +170,31 @@ def test_cell_table_keys_on_layout(tmp_path):
     tab = rocprof.cell_table([rocprof.counter_rows(str(p))], man)
     assert set(tab) == {(128 << 20, 16, "round_robin", 2), (128 << 20, 16, "strided", 2)}
     assert tab[(128 << 20, 16, "strided", 2)]["TCC_HIT_sum"] == 51.5
+
+
+def test_cells_cli_reads_the_fetch_scale_from_the_copies(tmp_path, capsys):
+    """`cells --calib-bytes` takes the FETCH_SIZE scale from the device
+    copies of the FETCH_SIZE pass, and says so in the header."""
+    import json
+    K4 = "void ilp::plain_kload<4, 16, 3>(ilp::PlainArgs)"
+    man = [{"bytes": 1 << 30, "waves_per_cu": 4, "K": 4, "order": "asc", "warmup": r == 0}
+           for r in range(3)]
+    m = tmp_path / "m.json"
+    m.write_text(json.dumps(man))
+    f = tmp_path / "f_counter_collection.csv"
+    _write_cc(f, [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0),
+                  (K4, "FETCH_SIZE", 1.0), (K4, "FETCH_SIZE", 524288.0),
+                  (K4, "FETCH_SIZE", 524290.0)])
+    h = tmp_path / "h_counter_collection.csv"
+    _write_cc(h, [(K4, "TCC_HIT_sum", 5.0)] * 3)
+    out = tmp_path / "cells.txt"
+    assert rocprof.main(["cells", "--manifest", str(m), "--counters", str(f), str(h),
+                         "--calib-bytes", str(1 << 30), "--out", str(out)]) == 0
+    text = out.read_text()
+    assert "# FETCH_SIZE scale (device copies of known size): 2" in text
+    row = [ln for ln in text.splitlines() if ln.startswith(f"{1 << 30} 4 4 asc:")][0]
+    assert f"fetch_bytes={524289.0 * 1024 * 2:.6g}" in row
+    with pytest.raises(SystemExit):
+        rocprof.main(["cells", "--manifest", str(m), "--counters", str(h),
+                      "--calib-bytes", str(1 << 30)])
+    capsys.readouterr()
