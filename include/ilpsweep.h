@@ -6,8 +6,8 @@
  * loads per iteration over a buffer far larger than the caches (Section 3,
  * "The axis K"), folds every loaded 32-bit word into a per-lane sink that the
  * compiler cannot drop (Section 3, "Instruments"), and the library reports
- * the attained bandwidth under a fixed-work control that matches total
- * issued logical loads across K (Section 3, "Fixed-work control"; Section
+ * the attained bandwidth under a fixed-work control that holds the total
+ * of issued logical loads equal for every K (Section 3, "Fixed-work control"; Section
  * 4.2, "Exact-work accounting").
  *
  * Conventions for every entry point below

@@ -13,9 +13,9 @@ Global Loads on the NVIDIA H100"):
 * ``plan``      - the fixed-work control of Section 3 ("Fixed-work control")
   and the exact-work accounting of Section 4.2 ("Exact-work accounting"):
   iteration counts, issued logical loads and the K-set mismatch.
-* ``checksums`` - the address map (Section 3: every warp's access is
-  contiguous and fully coalesced at every K; only the per-thread offered
-  count changes) and the per-lane / per-wave / global wrapping-sum and XOR
+* ``checksums`` - the address map (Section 3: whatever K is, a wave's
+  loads stay one contiguous, coalesced run; K only sets how many loads
+  each lane has outstanding) and the per-lane / per-wave / global wrapping-sum and XOR
   sinks of Section 3 ("Instruments").
 * ``brute``     - a lane-by-lane pure-Python simulation for tiny inputs, used
   to pin ``checksums``.

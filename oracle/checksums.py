@@ -7,8 +7,9 @@ sum and a 32-bit XOR, and reduces them over the lanes of a wave and over
 the grid with the same two operators.  Both operators are associative and
 commutative, so the result depends only on WHICH words each lane loads.
 
-Address map (Section 3, "Fixed-work control": the warp access is contiguous
-and fully coalesced at every K; only the per-thread offered count changes):
+Address map (Section 3, "Fixed-work control": whatever K is, a wave's loads
+stay one contiguous, coalesced run; K only sets how many loads each lane has
+outstanding):
 
     work unit     wave-group q = 0 .. Q-1, dealt to the waves round robin
                   (wave w of n_waves handles q = w, w + n_waves, ...) or in

@@ -1,11 +1,10 @@
 """Fixed-work control and exact-work accounting (oracle side).
 
-Section 3 ("Fixed-work control") sets each cell's iteration count to
-L / (threads x K) for a fixed target load count L, so that total issued
-logical loads match across K.  Section 4.2 ("Exact-work accounting") states
-that "matched" means the exact product of iteration count and per-thread
-offered count, and that its maximum mismatch over K in {1,2,4,8} is printed
-as 0.024576 %.
+Section 3 ("Fixed-work control") divides L, the target number of logical
+loads, by threads x K to get a cell's iteration count, so that every K
+issues about the same number of logical loads.  Section 4.2 ("Exact-work accounting")
+judges the match on iterations times loads per thread, counted exactly,
+and prints the largest mismatch over K in {1,2,4,8} as 0.024576 %.
 
 Three ways of turning (L, K, grid) into work are written out here:
 

@@ -3,14 +3,14 @@
 Section 3 ("Timing, residency, statistics") and Section 4.2 fix the
 reporting rules this module implements:
 
-* the unit is the kernel launch; a cell's figure is the median over its
+* one kernel launch is one sample; a cell's figure is the median over its
   launches, and the best launch is kept as a separate raw field
   (Section 4.1 reports median and best-of-N side by side);
 * the post-peak change is (B(K=8) - B(K=2)) / B(K=2) on per-K medians
   (Section 4.2, Table 1), and per-launch paired changes are reported too
   (Section 4.2, "Repeatability");
-* peak K and the knee follow a 95 % plateau rule with a stable three-cell
-  tail (Section 3; Section 4.2, "Prevalence").  The paper does not spell
+* peak K and the knee follow a 95 % plateau rule whose last three cells
+  must stay on the plateau (Section 3; Section 4.2, "Prevalence").  The paper does not spell
   the rule out; the reading used here: B* is the largest median, peak K
   the smallest K attaining it, knee the smallest K with B >= 0.95 B*;
   a curve is "saturating" if its last three cells are all >= 0.95 B*,
