@@ -94,7 +94,8 @@ def parse():
                     help="also run plain device copies of 1 GiB (counter scale)")
     ap.add_argument("--only", default=None,
                     choices=["c3", "c4", "c5a", "c5b", "c3counters", "c2counters",
-                             "c4counters", "c4stalls", "f3counters", "f3ksweep", "next"],
+                             "c4counters", "c4stalls", "f3counters", "f3ksweep", "next",
+                             "fabric"],
                     help="run only one extra configuration (no K sweep); "
                          "the *counters modes and c4stalls run cells one launch "
                          "per call for a separate rocprofv3 counter run")
@@ -448,6 +449,21 @@ def main():
             with open(a.manifest, "w") as f:
                 json.dump(man, f)
         print(json.dumps({"only": a.only, "launches": len(man)}))
+        return 0
+    if a.only == "fabric":
+        # the XCD-subset and per-XCD-share reads of the 1 GiB sweep buffer
+        # alone, for a kernel trace of their own
+        buf = sweeps.device_buffer(1 << 30, sweeps.SEED_BASE + 1)
+        rows = {}
+        for name, fn, kw in (("fabric_by_xcd", sweeps.fabric_by_xcd, {"manifest": a.manifest}),
+                             ("xcd_weighting", sweeps.xcd_weighting, {})):
+            try:
+                rows[name] = fn(buf, 1 << 30, policy=policy, **kw)
+            except isw.SweepError as e:
+                rows[name + "_error"] = str(e)
+        if a.json_out:
+            report.write_detail({"only": a.only, "rows": rows}, a.json_out)
+        print(json.dumps({"only": a.only, "detail": a.json_out, "rows": sorted(rows)}))
         return 0
     if a.only == "c2counters":
         man = sweeps.k_counter_pass(policy=policy, manifest=a.manifest)

@@ -199,7 +199,7 @@ def attribute(rows, manifest, kernel_substr="plain_kload"):
     return out
 
 
-CELL_KEYS = ("path", "policy", "bytes", "waves_per_cu", "layout", "K", "order")
+CELL_KEYS = ("path", "policy", "bytes", "waves_per_cu", "layout", "K", "order", "mask")
 
 
 def cell_key(m):
@@ -246,6 +246,29 @@ def cell_table(runs, manifest, fetch_scale=None, kernel_substr="plain_kload",
     return table
 
 
+def trace_cells(trace, manifest, kernel_substr):
+    """Per cell of a launch manifest: the kernel durations of a trace run,
+    paired in start order with the manifest's launches, warm-ups dropped;
+    median, range and count in ns, and decimal GB/s at the median where the
+    manifest gives each launch's issued bytes (``issued_bytes``)."""
+    sel = [r for r in trace_rows(trace) if kernel_substr in r["kernel"]]
+    if len(sel) != len(manifest):
+        raise ValueError(f"{len(sel)} {kernel_substr} dispatches for {len(manifest)} launches")
+    cells = {}
+    for m, r in zip(manifest, sel):
+        if m["warmup"] or r["ns"] is None:
+            continue
+        c = cells.setdefault(cell_key(m), {"ns": [], "bytes": m.get("issued_bytes")})
+        c["ns"].append(r["ns"])
+    out = {}
+    for key, c in sorted(cells.items()):
+        row = med_range(c["ns"])
+        if c["bytes"]:
+            row["gbps"] = c["bytes"] / row["median"]
+        out[key] = row
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="rocprofv3 CSV summaries")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -276,7 +299,35 @@ def main(argv=None):
     c3.add_argument("--xccs", type=int, default=None)
     c3.add_argument("--command", action="append", default=[])
     c3.add_argument("--out", default=None)
+    tc = sub.add_parser("trace-cells", help="per-cell kernel durations from a manifest")
+    tc.add_argument("--manifest", required=True)
+    tc.add_argument("--trace", required=True)
+    tc.add_argument("--kernel", required=True, help="substring naming the manifest's kernels")
+    tc.add_argument("--command", action="append", default=[])
+    tc.add_argument("--note", action="append", default=[])
+    tc.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    if a.cmd == "trace-cells":
+        import json
+        with open(a.manifest) as f:
+            man = json.load(f)
+        tab = trace_cells(a.trace, man, a.kernel)
+        lines = ["# rocprofv3 per-cell kernel durations (generated by paper_2608_15764_amd.rocprof)"]
+        lines += [f"# command: {c}" for c in a.command]
+        lines += [f"# {n}" for n in a.note]
+        keys = [k for k in CELL_KEYS if man and k in man[0]]
+        lines.append(f"# {' '.join(keys)}: median / min / max ns over non-warm-up launches, "
+                     "GB/s at the median")
+        for key, row in tab.items():
+            gb = f" gbps={row['gbps']:.1f}" if "gbps" in row else ""
+            lines.append(f"{' '.join(map(str, key))}: median_ns={row['median']:.0f} "
+                         f"min_ns={row['min']:.0f} max_ns={row['max']:.0f} n={row['n']}{gb}")
+        text = "\n".join(lines) + "\n"
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(text)
+        sys.stdout.write(text)
+        return 0
     if a.cmd == "cells":
         import json
         with open(a.manifest) as f:

@@ -892,25 +892,31 @@ FABRIC_MASKS = (("one", tuple(1 << x for x in range(8))),
 
 
 def fabric_by_xcd(buf, nbytes, waves_list=(4, 8), policy=isw.CACHE_BYPASS_L1_NT, n=5,
-                  masks=FABRIC_MASKS):
+                  masks=FABRIC_MASKS, manifest=None):
     """Where the plateau's ceiling sits: the plain K = 8 read run only by the
     workgroups of chosen XCDs (one XCD, a group of four that share a path,
     two or three from each group, all eight), each mask timed in ``n``
     launches after a warm-up.  Every active wave's XCC_ID is checked against
-    the XCD its workgroup index names (``misplaced_waves``)."""
+    the XCD its workgroup index names (``misplaced_waves``).  With
+    ``manifest`` (a path), every launch is listed in order for a separate
+    kernel-trace run."""
     import numpy as np
     dt = wave_rec_dtype()
     n_cus = isw.sweep_device_info()["num_cus"]
     rec = torch.zeros(n_cus * max(waves_list) * dt.itemsize, dtype=torch.uint8, device="cuda")
-    out = {}
+    out, launches = {}, []
     for w in waves_list:
         rows, by_class = {}, {}
         for cls, ms in masks:
             for m in ms:
                 opts = isw.make_opts(cache_policy=policy, wave_out=rec)
-                isw.sweep_xcd_subset(buf, nbytes, w, m, opts)           # warm-up
+                r0 = isw.sweep_xcd_subset(buf, nbytes, w, m, opts)      # warm-up
                 runs = [isw.sweep_xcd_subset(buf, nbytes, w, m, opts) for _ in range(n)]
                 r = runs[-1]
+                for i, x in enumerate([r0] + runs):
+                    launches.append({"path": "xcd_subset", "waves_per_cu": w,
+                                     "mask": f"{m:#04x}", "issued_bytes": x["issued_bytes"],
+                                     "rep": i, "warmup": i == 0})
                 a = rec[: r["waves"] * dt.itemsize].cpu().numpy().view(dt)
                 bits = [x for x in range(8) if m >> x & 1]
                 want = np.array([bits[(aw // 4) % len(bits)] for aw in range(r["waves"])])
@@ -926,6 +932,9 @@ def fabric_by_xcd(buf, nbytes, waves_list=(4, 8), policy=isw.CACHE_BYPASS_L1_NT,
         out[w] = {"masks": rows,
                   "by_class": {c: [round(min(v), 1), round(max(v), 1)] for c, v in by_class.items()}}
     del rec
+    if manifest:
+        with open(manifest, "w") as f:
+            json.dump(launches, f)
     return out
 
 

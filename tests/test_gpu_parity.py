@@ -1,5 +1,7 @@
 """Parity of the HIP path against the CPU oracle, at sizes the oracle
 finishes in seconds (several tiles, ragged tails, wrap-around)."""
+import json
+
 import numpy as np
 import pytest
 
@@ -801,7 +803,7 @@ def test_sweep_drivers_run_small():
     assert sg["best_gbps"] >= sg["median_gbps"] > 0
 
 
-def test_new_bench_rows_run_small():
+def test_new_bench_rows_run_small(tmp_path):
     """The rows added to the benchmark, on small inputs: the gate's verdict,
     the gap split, the regime map on several backends, coverage in the
     order/footprint and allocation rows, and the oracle-checked batch."""
@@ -820,9 +822,14 @@ def test_new_bench_rows_run_small():
                                waves, Ks)
     xw = sweeps.xcd_weighting(buf, nbytes, waves_list=(4,), rounds=1, n=1)
     assert len(xw[4]["rounds"]) == 2 and abs(sum(xw[4]["rounds"][1]["shares"]) - 1) < 1e-3
+    man_path = tmp_path / "fabric_manifest.json"
     fb = sweeps.fabric_by_xcd(buf, nbytes, waves_list=(4,), n=1,
-                              masks=(("one", (0x01,)), ("all", (0xFF,))))
+                              masks=(("one", (0x01,)), ("all", (0xFF,))), manifest=str(man_path))
     assert set(fb[4]["masks"]) == {"0x01", "0xff"}
+    man = json.loads(man_path.read_text())
+    assert [(m["mask"], m["warmup"]) for m in man] == [("0x01", True), ("0x01", False),
+                                                       ("0xff", True), ("0xff", False)]
+    assert man[3]["issued_bytes"] == fb[4]["masks"]["0xff"]["bytes"]
     assert all(m["misplaced_waves"] == 0 and m["gbps"] > 0 for m in fb[4]["masks"].values())
     prod = gap["ceiling_frac_of_peak"] * (1 - gap["tail_loss"]) * gap["residual_frac"]
     assert prod == pytest.approx(gap["kernel_frac"], rel=1e-3)

@@ -198,3 +198,46 @@ def test_cells_cli_reads_the_fetch_scale_from_the_copies(tmp_path, capsys):
         rocprof.main(["cells", "--manifest", str(m), "--counters", str(h),
                       "--calib-bytes", str(1 << 30)])
     capsys.readouterr()
+
+
+def _write_trace(path, rows):
+    fields = ["Kernel_Name", "Dispatch_Id", "Start_Timestamp", "End_Timestamp"]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for i, (k, s, e) in enumerate(rows):
+            w.writerow({"Kernel_Name": k, "Dispatch_Id": i + 1, "Start_Timestamp": s,
+                        "End_Timestamp": e})
+
+
+def test_trace_cells_pairs_durations_with_the_manifest(tmp_path, capsys):
+    """Kernel durations of a trace, paired in start order with a launch
+    manifest: warm-ups dropped, other kernels ignored, GB/s at the median."""
+    import json
+    X = "void ilp::xcd_subset<3>(ilp::XcdArgs)"
+    man, rows, t = [], [], 1000
+    for mask, dur in (("0x01", 800), ("0xff", 150)):
+        for rep in range(4):
+            man.append({"path": "xcd_subset", "waves_per_cu": 4, "mask": mask,
+                        "issued_bytes": 1200, "rep": rep, "warmup": rep == 0})
+            d = 5000 if rep == 0 else dur + rep
+            rows.append((X, t, t + d))
+            rows.append(("ilp::finish_cells(...)", t + d + 10, t + d + 20))
+            t += d + 100
+    p = tmp_path / "x_kernel_trace.csv"
+    _write_trace(p, rows[::-1])                       # file order does not matter
+    tab = rocprof.trace_cells(str(p), man, "xcd_subset")
+    assert set(tab) == {("xcd_subset", 4, "0x01"), ("xcd_subset", 4, "0xff")}
+    r = tab[("xcd_subset", 4, "0xff")]
+    assert (r["median"], r["min"], r["max"], r["n"]) == (152, 151, 153, 3)
+    assert r["gbps"] == pytest.approx(1200 / 152)
+    with pytest.raises(ValueError):
+        rocprof.trace_cells(str(p), man[:-1], "xcd_subset")
+    m = tmp_path / "m.json"
+    m.write_text(json.dumps(man))
+    out = tmp_path / "t.txt"
+    assert rocprof.main(["trace-cells", "--manifest", str(m), "--trace", str(p),
+                         "--kernel", "xcd_subset", "--out", str(out)]) == 0
+    text = out.read_text()
+    assert "xcd_subset 4 0x01: median_ns=802 min_ns=801 max_ns=803 n=3 gbps=1.5" in text
+    capsys.readouterr()
