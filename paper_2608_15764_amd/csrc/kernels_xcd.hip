@@ -11,9 +11,9 @@ namespace ilp {
 template <int POL>
 __global__ __launch_bounds__(kPlainWgThreads) void xcd_subset(XcdArgs a) {
   const uint64_t t0 = wall_ticks();
-  // The dispatcher deals workgroups to the 8 XCDs in turn, starting at the
-  // XCD after the one the previous launch ended on, so workgroup b runs on
-  // XCD (b + r) mod 8 for some r of this launch.  Each round of eight
+  // The dispatcher deals workgroups to the 8 XCDs in turn, but the XCD it
+  // starts on changes from launch to launch, so workgroup b runs on XCD
+  // (b + r) mod 8 for an r fixed within the launch.  Each round of eight
   // workgroups (b >> 3) then puts one on every XCD, and numbering the
   // active ones by (round, rank of the XCD in the mask) is dense whatever r
   // is.  The XCD itself comes from the hardware register.
