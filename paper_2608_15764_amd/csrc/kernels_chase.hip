@@ -29,6 +29,9 @@ __global__ __launch_bounds__(64) void chase(ChaseArgs a) {
   uint32_t idx = a.start;
 #pragma unroll 1
   for (uint32_t i = 0; i < a.warm; ++i) idx = chase_load<POL>(a.buf, a.n_bytes, idx);
+  // the clocks bracket exactly the timed hops: the last warm-up load has
+  // landed before they start, the last timed one before they stop
+  wait_vmcnt<0>();
   const uint64_t r0 = wall_ticks();
   const uint64_t m0 = __builtin_amdgcn_s_memtime();
 #pragma unroll 1
@@ -42,6 +45,7 @@ __global__ __launch_bounds__(64) void chase(ChaseArgs a) {
 #pragma unroll 1
   for (uint32_t i = a.n_samples; i < a.steps; ++i)
     idx = chase_load<POL>(a.buf, a.n_bytes, idx);
+  wait_vmcnt<0>();
   const uint64_t r1 = wall_ticks();
   const uint64_t m1 = __builtin_amdgcn_s_memtime();
   for (uint32_t i = 0; i < a.n_samples; ++i) a.samples[i] = cyc[i];
