@@ -212,3 +212,18 @@ def test_gap_split_factors_multiply_to_the_kernel_fraction():
     assert abs(g["kernel_frac"] - g["ceiling_frac_of_peak"]) < 1e-12
     with pytest.raises(ValueError):
         stats.gap_split([])
+
+
+def test_front_duplicates_random_cells():
+    """The same brute force over random small cells of every order."""
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=120, deadline=None, derandomize=True)
+    @given(order=st.integers(0, 2), K=st.integers(1, 6), nw=st.integers(1, 12),
+           Q=st.integers(1, 60), segs=st.integers(1, 40))
+    def check(order, K, nw, Q, segs):
+        nv = 64 * segs
+        assert stats.front_duplicates(order, K, nw, Q, nv, max_iters=10**6) == \
+            pytest.approx(_front_brute(order, K, nw, Q, nv), abs=0), (order, K, nw, Q, nv)
+
+    check()
