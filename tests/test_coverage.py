@@ -56,3 +56,23 @@ def test_product_closed_form_matches_the_walk(alloc, V, K, L, n_waves, order):
     want = coverage.line_coverage(alloc, V, K, Q, n_waves, order)
     got = stats.line_coverage(alloc, V, 64 * K * Q)
     assert got == want
+
+
+def test_walk_and_closed_form_on_random_cells():
+    """The walk against the lane brute force, and the product's closed
+    form against the walk, over random small cells of every order."""
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=150, deadline=None, derandomize=True)
+    @given(order=st.sampled_from([plan.ROUND_ROBIN, plan.BLOCKED, plan.STRIDED]),
+           V=st.sampled_from([4, 8, 16]), K=st.integers(1, 9), Q=st.integers(1, 30),
+           n_waves=st.integers(1, 9), segs=st.integers(1, 24))
+    def check(order, V, K, Q, n_waves, segs):
+        alloc = 64 * V * segs
+        brute = coverage.lane_line_reads(alloc, V, K, Q, n_waves, order)
+        c = coverage.line_coverage(alloc, V, K, Q, n_waves, order)
+        assert c["unique_lines"] == sum(1 for x in brute if x)
+        assert c["line_reads"] == sum(brute) and c["max_reads"] == max(brute)
+        assert stats.line_coverage(alloc, V, 64 * K * Q) == c
+
+    check()
