@@ -231,3 +231,28 @@ def test_range_sinks_many_combines_pieces():
     want = [checksums.range_sinks(*r) for r in ranges]
     assert checksums.range_sinks_many(ranges, threads=3, piece=1000) == want
     assert checksums.range_sinks_many(ranges, threads=1, piece=333) == want
+
+
+def test_vectorised_oracle_matches_brute_force_on_random_cells():
+    """Per-lane and per-wave sinks of the vectorised oracle against the
+    lane-by-lane simulation, over random small cells of every order (random
+    words, wrap, ragged deals, groups larger than the buffer)."""
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=60, deadline=None, derandomize=True)
+    @given(order=st.sampled_from([plan.ROUND_ROBIN, plan.BLOCKED, plan.STRIDED]),
+           V=st.sampled_from([4, 8, 16]), K=st.integers(1, 6), Q=st.integers(1, 12),
+           nw=st.integers(1, 5), segs=st.integers(1, 9), seed=st.integers(0, 2**32 - 1))
+    def check(order, V, K, Q, nw, segs, seed):
+        nbytes = V * 64 * segs
+        w = splitmix.buffer_words(seed, nbytes)
+        lanes = brute.simulate(w, V, K, Q, nw, blocked=order == plan.BLOCKED,
+                               strided=order == plan.STRIDED)
+        s, x = checksums.per_lane(w, V, K, Q, nw, order=order)
+        for (wave, lane), (ls, lx) in lanes.items():
+            assert (s[wave, lane], x[wave, lane]) == (ls, lx)
+        bs, bx = brute.per_wave(lanes, nw)
+        ws, wx = checksums.per_wave(w, V, K, Q, nw, order=order, chunk_groups=2)
+        assert ws.tolist() == bs and wx.tolist() == bx
+
+    check()
