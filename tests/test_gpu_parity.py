@@ -317,6 +317,60 @@ def test_two_stream_split_matches_oracle(D, wa, wb, kind_b):
             assert (same["sum32"], same["xor32"]) == (split_["sum32"], split_["xor32"])
 
 
+def _random_two_stream_cases(n=24, seed=20261205):
+    """Seeded random two-stream cells: mechanism of stream B, placement,
+    depth, waves of each stream (either may be 0), grid, buffer size and
+    target, and cache policy, drawn together."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        kind = ["lds_async", "plain"][int(rng.integers(2))]
+        split = bool(rng.integers(2))
+        D = int(rng.integers(1, 17))
+        wmax = 16 if split else 8
+        wa, wb = int(rng.integers(0, wmax + 1)), int(rng.integers(0, wmax + 1))
+        if wa + wb == 0 or (kind == "lds_async" and wb * D > 160):
+            continue
+        grid = int(rng.choice([16, 32])) if split else int(rng.integers(1, 7))
+        n_vec = 128 * int(rng.integers(1, 97))
+        L = 2 * 64 * D * int(rng.integers(1, 400)) + int(rng.integers(0, 2 * 64 * D))
+        out.append((kind, split, D, wa, wb, grid, n_vec, L, int(rng.integers(4))))
+    return out
+
+
+@pytest.mark.parametrize("kind_b,split,D,wa,wb,grid,n_vec,L,policy", _random_two_stream_cases())
+def test_two_stream_random_cells_match_oracle(kind_b, split, D, wa, wb, grid, n_vec, L, policy):
+    """Per-lane sinks of both streams against the oracle on random cells,
+    in one workgroup or split across CUs."""
+    print(f"two-stream case: {kind_b} split={split} D={D} wa={wa} wb={wb} grid={grid} "
+          f"n_vec={n_vec} L={L} policy={policy}", flush=True)
+    nbytes = n_vec * 16
+    buf = synth.random_bytes(nbytes, seed=n_vec + D + 10 * wa + 100 * wb, device="cuda")
+    per = grid // 2 if split else grid
+    na, nb = per * wa, per * wb
+    ro = recs(na + nb)
+    lo = lanes((na + nb) * 64)
+    opts = isw.make_opts(grid_wgs=grid, wave_out=ro, lane_out=lo, cache_policy=policy)
+    kb = isw.KIND_LDS_ASYNC if kind_b == "lds_async" else isw.KIND_PLAIN
+    fn = isw.sweep_two_stream_split if split else isw.sweep_two_stream_kind
+    ra, rb = fn(buf, nbytes, D, wa, wb, kb, L, opts)
+    words = host_words(buf)
+    (a0, an), (b0, bn) = checksums.two_stream_regions(n_vec)
+    gs, gx = decode_lanes(lo, na + nb)
+    La, Lb = L // 2, L - L // 2
+    for (base, nv, Ls, nw, off, res) in ((a0, an, La, na, 0, ra),
+                                         (b0, bn, Lb, nb, na, rb)):
+        if nw == 0:
+            assert res["issued_loads"] == 0
+            continue
+        p = oplan.wave_group(Ls, D, nw)
+        assert res["issued_loads"] == p["issued"] and res["waves"] == nw
+        ws, wx = checksums.per_lane(words, 16, D, p["Q"], nw, base=base, n_vec=nv)
+        assert np.array_equal(gs[off:off + nw], ws)
+        assert np.array_equal(gx[off:off + nw], wx)
+        assert (res["sum32"], res["xor32"]) == checksums.combine(ws, wx)
+
+
 def test_two_stream_split_places_streams_on_different_cus():
     """At one workgroup per CU the two streams share no CU, and every XCD
     holds as many CUs of each stream (from the waves' HW_ID / XCC_ID)."""
