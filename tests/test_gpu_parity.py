@@ -708,6 +708,49 @@ def test_xcd_split_matches_oracle(weights, w):
     assert r["iters_min"] == int(min(per_wave)) and r["iters_max"] == -int(-max(per_wave) // 1)
 
 
+def _random_xcd_cases(n=12, seed=20261206):
+    rng = np.random.default_rng(seed)
+    masks = [int(m) for m in rng.integers(1, 256, size=n)]
+    weights = []
+    while len(weights) < n:
+        wt = [0.0 if rng.random() < 0.25 else round(float(rng.uniform(0.05, 2.0)), 3)
+              for _ in range(8)]
+        if sum(wt) > 0:
+            weights.append(wt)
+    ws = [int(rng.choice([4, 8, 16])) for _ in range(n)]
+    return list(zip(masks, weights, ws))
+
+
+@pytest.mark.parametrize("mask,weights,w", _random_xcd_cases())
+def test_xcd_reads_random_masks_and_weights(mask, weights, w):
+    """Random XCD subsets and random per-XCD weights: each read covers its
+    prefix once (global sinks against the oracle) and every wave ran on
+    the XCD its number names."""
+    nbytes = 64 << 20
+    buf = synth.random_bytes(nbytes, seed=mask + 7 * w, device="cuda")
+    words = host_words(buf)
+    n_cus = isw.sweep_device_info()["num_cus"]
+    print(f"xcd random: mask {mask:#04x}, weights {weights}, {w} waves/CU", flush=True)
+    n_act = (n_cus * w // 32) * bin(mask).count("1") * 4
+    ro = recs(max(n_act, n_cus * w // 8 * 8))
+    r = isw.sweep_xcd_subset(buf, nbytes, w, mask, isw.make_opts(wave_out=ro))
+    groups = (nbytes // 16) // (n_act * 512)
+    assert r["waves"] == n_act and r["issued_loads"] == n_act * groups * 512
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words[: r["issued_loads"] * 4])
+    got = decode_recs(ro)["xcc_id"][:n_act].astype(np.int64) & 0xF
+    assert np.array_equal(got, [_xcd_of_active_wave(aw, mask) for aw in range(n_act)])
+    per_xcd = n_cus * w // 8
+    total = (nbytes // 16) // 512
+    tw = float(sum(weights))
+    shares = [int(total * (v / tw)) for v in weights]
+    bits = [x for x in range(8) if shares[x]]
+    r = isw.sweep_xcd_split(buf, nbytes, w, weights, isw.make_opts(wave_out=ro))
+    assert r["waves"] == len(bits) * per_xcd and r["issued_loads"] == sum(shares) * 512
+    assert (r["sum32"], r["xor32"]) == checksums.whole_buffer(words[: r["issued_loads"] * 4])
+    got = decode_recs(ro)["xcc_id"][: r["waves"]].astype(np.int64) & 0xF
+    assert np.array_equal(got, np.repeat(bits, per_xcd))
+
+
 def test_xcd_split_rejects_bad_arguments():
     buf = dev_bytes(1 << 20)
     for wts in ([0] * 8, [1, -1, 1, 1, 1, 1, 1, 1], [float("nan")] + [1] * 7,
