@@ -7,8 +7,8 @@
  * "The axis K"), folds every loaded 32-bit word into a per-lane sink that the
  * compiler cannot drop (Section 3, "Instruments"), and the library reports
  * the attained bandwidth under a fixed-work control that holds the total
- * of issued logical loads equal for every K (Section 3, "Fixed-work control"; Section
- * 4.2, "Exact-work accounting").
+ * of issued logical loads equal for every K (Section 3, "Fixed-work
+ * control"; Section 4.2, "Exact-work accounting").
  *
  * Conventions for every entry point below
  * ---------------------------------------
@@ -79,7 +79,7 @@ extern "C" {
 /* ------------------------------------------------------- work-group order */
 /* How wave-groups are dealt to the waves (the address ordering of Section
  * 4.2's proposed discriminating experiment; coalescing, occupancy and bytes
- * are the same under both).  Plain kernel only. */
+ * are the same under all three).  Plain kernel only. */
 #define SWEEP_ORDER_ROUND_ROBIN 0  /* wave w: q = w, w + n_waves, ...        */
 #define SWEEP_ORDER_BLOCKED     1  /* wave w: q = w*G .. w*G+G-1,
                                       G = ceil(Q / n_waves)                    */
