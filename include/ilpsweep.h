@@ -238,8 +238,10 @@ int sweep_calibrate_clock(double seconds, double* hz);
  * count the grid is sized for.  Errors: SWEEP_EINVAL (K not in 1..16,
  * vec_width not 4/8/16, waves_per_cu not a multiple of 4 in 4..32, bytes 0,
  * L too small for one wave-group in fixed-work mode, fixed_iters 0 in
- * fixed-iteration mode, unknown mode or order), SWEEP_EALIGN (bytes not a multiple
- * of 64 * vec_width, so that no 64-lane segment straddles the buffer end). */
+ * fixed-iteration mode, unknown mode or order, more than 2^32 - 1
+ * iterations for some wave, issued bytes beyond 64 bits), SWEEP_EALIGN
+ * (bytes not a multiple of 64 * vec_width, so that no 64-lane segment
+ * straddles the buffer end). */
 int sweep_plan(size_t bytes, int K, int vec_width, int waves_per_cu,
                uint64_t total_logical_loads, int mode, uint32_t fixed_iters,
                uint32_t num_cus, uint32_t grid_wgs, int order,

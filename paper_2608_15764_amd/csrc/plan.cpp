@@ -90,8 +90,13 @@ int plan_cell(const PlanIn& in, Plan* out, std::string* err) {
   }
   if (o.Q == 0) return bad(err, SWEEP_EINVAL, "L is smaller than one wave-group per wave");
   o.issued_loads = 64ull * K * o.Q;
+  if (o.issued_loads > UINT64_MAX / (uint64_t)in.V)
+    return bad(err, SWEEP_EINVAL, "issued bytes do not fit 64 bits");
   o.issued_bytes = o.issued_loads * (uint64_t)in.V;
   p.G = (o.Q + nw - 1) / nw;
+  // per-wave iteration counts are reported in 32 bits
+  if (p.G > UINT32_MAX)
+    return bad(err, SWEEP_EINVAL, "a wave would run more than 2^32 - 1 iterations");
   if (in.order == SWEEP_ORDER_BLOCKED) {
     // wave w handles min(G, max(0, Q - w G)) groups
     const uint64_t last = (nw - 1) * p.G;

@@ -218,7 +218,7 @@ def test_front_duplicates_random_cells():
     """The same brute force over random small cells of every order."""
     from hypothesis import given, settings, strategies as st
 
-    @settings(max_examples=120, deadline=None, derandomize=True)
+    @settings(max_examples=120, deadline=None, derandomize=not os.environ.get("ILPSWEEP_HYPOTHESIS_RANDOM"))
     @given(order=st.integers(0, 2), K=st.integers(1, 6), nw=st.integers(1, 12),
            Q=st.integers(1, 60), segs=st.integers(1, 40))
     def check(order, K, nw, Q, segs):
