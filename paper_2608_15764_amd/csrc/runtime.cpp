@@ -543,6 +543,8 @@ int two_stream_impl(const void* buf, size_t bytes, int depth, int waves_plain,
   if (bytes % 2048 || reinterpret_cast<uintptr_t>(buf) % 16)
     return fail(SWEEP_EALIGN, "two-stream needs a 16-byte aligned buffer, bytes % 2048 == 0");
   if (total_logical_loads == 0) return fail(SWEEP_EINVAL, "total_logical_loads is 0");
+  if (total_logical_loads > UINT64_MAX / 16)
+    return fail(SWEEP_EINVAL, "issued bytes do not fit 64 bits");
   const int pol = opt ? opt->cache_policy : SWEEP_CACHE_DEFAULT;
   if (pol < 0 || pol > 3) return fail(SWEEP_EINVAL, "unknown cache policy");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -569,6 +571,11 @@ int two_stream_impl(const void* buf, size_t bytes, int depth, int waves_plain,
   if (waves_async) region_plan(a.n_vec_b, depth, Lb, wg_b * a.waves_b, &a.Q_b, &a.stride_b);
   if ((waves_plain && a.Q_a == 0) || (waves_async && a.Q_b == 0))
     return fail(SWEEP_EINVAL, "L is smaller than one wave-group per stream");
+  // per-wave iteration counts are reported in 32 bits
+  const uint64_t nwa = (uint64_t)wg_a * a.waves_a, nwb = (uint64_t)wg_b * a.waves_b;
+  if ((nwa && (a.Q_a + nwa - 1) / nwa > UINT32_MAX) ||
+      (nwb && (a.Q_b + nwb - 1) / nwb > UINT32_MAX))
+    return fail(SWEEP_EINVAL, "a wave would run more than 2^32 - 1 iterations");
   const uint32_t threads =
       (uint32_t)(split ? std::max(waves_plain, waves_async) : waves_plain + waves_async) * 64u;
   const uint32_t ring = b_plain ? 0u : (uint32_t)waves_async * (uint32_t)depth * 1024u;

@@ -529,6 +529,16 @@ def test_host_validation_errors():
             isw.sweep_two_stream_split(buf, 1 << 20, 4, wa, wb, isw.KIND_PLAIN, 1 << 16,
                                        isw.make_opts(grid_wgs=grid))
         assert e.value.code == isw.EINVAL
+    # one wave per stream and 2^33 wave-groups each: iteration counts
+    # beyond 32 bits; and a target whose issued bytes pass 64 bits
+    for L in (1 << 40, 1 << 61):
+        with pytest.raises(isw.SweepError) as e:
+            isw.sweep_two_stream_kind(buf, 1 << 20, 1, 1, 1, isw.KIND_PLAIN, L,
+                                      isw.make_opts(grid_wgs=1))
+        assert e.value.code == isw.EINVAL
+    with pytest.raises(isw.SweepError) as e:
+        isw.sweep_plain(buf, 1 << 20, 1, 4, 4, 1 << 40, isw.make_opts(grid_wgs=1))
+    assert e.value.code == isw.EINVAL
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_reduce_fp(buf, 10, 9)
     assert e.value.code == isw.EINVAL
