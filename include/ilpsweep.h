@@ -447,7 +447,7 @@ int sweep_autotune(const void* buf, size_t bytes,
  * loads in flight at waves_per_cu = 4 and four above.  Deterministic for a
  * fixed grid and waves_per_cu.
  *   payload  device, 16-byte aligned; n_elems elements of `dtype`
- *   n_elems  any count (0 gives 0.0)
+ *   n_elems  any count (0 gives 0.0) whose bytes fit 64 bits
  *   dtype    SWEEP_F32, SWEEP_BF16 or SWEEP_FP8_E4M3
  *   waves_per_cu  4..32, multiple of 4
  *   sum      host, receives the result

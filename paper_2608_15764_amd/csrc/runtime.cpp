@@ -1170,10 +1170,11 @@ int sweep_reduce_fp(const void* payload, size_t n_elems, int dtype,
   if (n_elems && !payload) return fail(SWEEP_EINVAL, "payload pointer is NULL");
   if (reinterpret_cast<uintptr_t>(payload) % 16)
     return fail(SWEEP_EALIGN, "payload must be 16-byte aligned");
+  const size_t esz = dtype == SWEEP_F32 ? 4 : dtype == SWEEP_BF16 ? 2 : 1;
+  if (n_elems > SIZE_MAX / esz) return fail(SWEEP_EINVAL, "payload bytes do not fit 64 bits");
   std::lock_guard<std::mutex> lk(g_mu);
   Dev* d = nullptr;
   SW_TRY(current_dev(&d));
-  const size_t esz = dtype == SWEEP_F32 ? 4 : dtype == SWEEP_BF16 ? 2 : 1;
   const uint32_t grid = (opt && opt->grid_wgs) ? opt->grid_wgs
                                                : d->num_cus * (uint32_t)waves_per_cu / 4u;
   ReduceArgs a;

@@ -171,3 +171,22 @@ def test_planner_rejects_unknown_mode(isw):
     with pytest.raises(isw.SweepError) as e:
         isw.sweep_plan(1 << 20, 2, 16, 8, 1000, num_cus=256, order=3)
     assert e.value.code == -1
+
+
+def test_argument_checks_that_precede_any_device_work(isw):
+    """Checks every entry point makes before it touches a device, run on the
+    host: sizes whose byte counts overflow, NULL and misaligned pointers."""
+    cases = [
+        (lambda: isw.sweep_reduce_fp(16, 2**63, isw.F32, 4), isw.EINVAL),
+        (lambda: isw.sweep_reduce_fp(16, 10, 9, 4), isw.EINVAL),
+        (lambda: isw.sweep_reduce_fp(8, 10, isw.F32, 4), isw.EALIGN),
+        (lambda: isw.sweep_reduce_fp(16, 10, isw.F32, 6), isw.EINVAL),
+        (lambda: isw.sweep_fill_u32(0, 64, 1), isw.EINVAL),
+        (lambda: isw.sweep_fill_u32(16, 6, 1), isw.EALIGN),
+        (lambda: isw.sweep_chase(16, 1 << 32, 0, 0, 10), isw.EINVAL),
+        (lambda: isw.sweep_chase(16, 4096, 1024, 0, 10), isw.EINVAL),
+    ]
+    for call, code in cases:
+        with pytest.raises(isw.SweepError) as e:
+            call()
+        assert e.value.code == code
